@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Throughput of the per-event |M|^2 path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic events:
+random numbers + RAMBO (fused sampler kernel) and SIGMAKIN (helicity
+amplitudes, colour-flow amplitudes, colour sum, helicity sum), for the
+gg -> t t~ g g workload (2^19 events, seed 3, sqrt(s) = 1500 GeV).
+The headline value is the FP64 path; the FP32-amplitude path is measured
+beside it.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "matrix elements/sec gg→tt̄gg on 1 GPU, FP64 vs mixed; % FP64/MFMA peak"
+PAPER_V100_GGTTGG = 5.2e5      # MEs/s, FP64, 524,288 events per iteration (paper, context)
+PEAK_FP64_VALU = 78.6e12       # FLOP/s, MI355X vector FP64 (256 CU x 4 SIMD x 16 lanes x FMA x 2.4 GHz)
+PEAK_FP32_VALU_UNPACKED = 78.6e12  # FLOP/s without packed-FP32 instructions (not used here)
+
+
+# ----------------------------------------------------------------------------- CPU baseline
+def _oracle_chunk(task):
+    proc, seed, start, count = task
+    import torch
+    torch.set_num_threads(1)
+    from oracle import me as orc
+    t0 = time.perf_counter()
+    _, p, _ = orc.sample(proc, seed, start, count)
+    orc.matrix_element(proc, p, chunk=64)
+    return count, time.perf_counter() - t0
+
+
+def cpu_baseline(proc, seed, per_worker, workers):
+    """Oracle (as it stands) on a bounded sample, one process per core."""
+    import multiprocessing as mp
+    tasks = [(proc, seed, w * per_worker, per_worker) for w in range(workers)]
+    ctx = mp.get_context('fork')
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_chunk, tasks)
+    wall = time.perf_counter() - t0
+    n = sum(c for c, _ in res)
+    return {"value": n / wall, "unit": "MEs/s", "cores": workers, "kind": "oracle",
+            "sample": f"events 0..{n - 1} of the workload (seed {seed}): RNG + RAMBO + |M|^2, "
+                      f"{workers} processes x 1 thread, {wall:.1f} s wall"}
+
+
+# ----------------------------------------------------------------------------- GPU
+def run_gpu(mg, torch, proc, prec, seed, nevt, steps, warmup):
+    eng = mg.MEEngine(proc, prec)
+    dev = eng.device
+    mom = eng.empty_mom(nevt)
+    wgt = torch.empty(nevt, dtype=torch.float64, device=dev)
+    me = torch.empty(nevt, dtype=torch.float64, device=dev)
+
+    def step():
+        eng.sample(seed, nevt, mom=mom, wgt=wgt)
+        eng.sigmakin(mom, nevt, me=me)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        eng.sample(seed, nevt, mom=mom, wgt=wgt)
+        evs[k][0].record(stream)
+        eng.sigmakin(mom, nevt, me=me)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_ms = [a.elapsed_time(b) for a, b in evs]
+    nonfinite = eng.count_nonfinite(me)
+    return eng, wall, k_ms, nonfinite
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=5)
+    ap.add_argument('--warmup', type=int, default=1)
+    ap.add_argument('--process', default='ggttgg')
+    ap.add_argument('--nevt', type=int, default=1 << 19)
+    ap.add_argument('--seed', type=int, default=3)
+    ap.add_argument('--precisions', default='fp64,fp32amp')
+    ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--cpu-events-per-worker', type=int, default=96)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(events shard trivially across GPUs, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        workers = max(1, min(16, os.cpu_count() or 1))
+        cpu = cpu_baseline(args.process, args.seed, args.cpu_events_per_worker, workers)
+
+    import torch
+    import paper_2106_12631_amd as mg
+    meta = json.load(open(os.path.join(ROOT, 'paper_2106_12631_amd', 'csrc', 'generated',
+                                       'meta.json')))[args.process]
+    results = {}
+    for prec in args.precisions.split(','):
+        eng, wall, k_ms, nonfinite = run_gpu(mg, torch, args.process, prec, args.seed, args.nevt,
+                                             args.steps, args.warmup)
+        nhel = eng.layout.nhel_good
+        flops_evt = (meta['flops_amp_per_hel'] + meta['flops_colour_per_hel']) * nhel
+        k_avg = sum(k_ms) / len(k_ms) / 1e3
+        achieved = flops_evt * args.nevt / k_avg
+        results[prec] = {
+            "value": args.nevt * args.steps / wall,
+            "ms_per_step": wall / args.steps * 1e3,
+            "sigmakin_ms": k_avg * 1e3,
+            "sigmakin_MEs_per_s": args.nevt / k_avg,
+            "nonfinite": nonfinite,
+            "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                         "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                         "flops_per_event": flops_evt},
+        }
+    head = results.get('fp64') or next(iter(results.values()))
+    line = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "MEs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": head["value"] / PAPER_V100_GGTTGG if args.process == 'ggttgg' else None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.process} {args.nevt} events seed {args.seed} "
+                               f"sqrt(s)=1500 GeV (Philox + RAMBO + |M|^2)",
+                   "process": args.process, "nevt": args.nevt, "seed": args.seed,
+                   "parallelism": "1 GPU, one event per lane"},
+        "roofline": head["roofline"],
+        "cpu_baseline": cpu,
+        "variants": results,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == '__main__':
+    main()

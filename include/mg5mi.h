@@ -1,0 +1,149 @@
+/* mg5mi.h -- C ABI of the per-event |M|^2 library for AMD MI355X (gfx950).
+ *
+ * The library evaluates, for baskets of independent events, the three
+ * components of the workflow in Sec. IV.a/IV.b of arxiv 2106.12631: a
+ * random-number generator, the RAMBO phase-space sampler and the
+ * matrix-element engine (SIGMAKIN: helicity amplitudes, colour-flow
+ * amplitudes, colour sum, helicity sum; Sec. II).  Every call works on one
+ * "iteration" of events held in caller-owned device arrays of fixed
+ * dimension (Sec. IV.b).
+ *
+ * Ownership and threading
+ *   - Every buffer pointer is a DEVICE pointer owned by the caller; the
+ *     library never allocates, frees or keeps caller memory.  Pointers must
+ *     be 8-byte aligned (MG_EALIGN otherwise).
+ *   - `stream` is a hipStream_t cast to void* (NULL = the null stream).
+ *     Calls enqueue work on it and return without synchronising, except
+ *     mg_create (which runs a small helicity-filtering pass and waits for
+ *     it) and mg_count_nonfinite's optional host copy.
+ *   - A handle is immutable after mg_create; any number of streams may use
+ *     it concurrently with disjoint outputs.
+ *
+ * Layouts (AoSoA, Sec. IV.b "AOSOA"; page sizes from mg_layout):
+ *   rnd  [ceil(nevt/neppR)][nrnd][neppR]    uniforms, irnd = 4*ifinal + k
+ *   mom  [ceil(nevt/neppM)][npar][4][neppM] (E, px, py, pz) per particle
+ *   flat arrays wgt, me, evtw, gbar: [nevt]
+ *   grad_rnd, grad_logw: same AoSoA layout as rnd
+ *   Event ievt sits in page ievt / nepp at slot ievt % nepp.  AoSoA buffers
+ *   must hold ceil(nevt/nepp)*nepp events; slots past nevt are not written.
+ *
+ * Errors: every entry point returns 0 on success or a negative MG_E* code;
+ * no C++ exception crosses the ABI.  Kernel launch failures are reported
+ * as MG_EHIP (from hipGetLastError after the launch).  Non-finite matrix
+ * elements are not errors: mg_count_nonfinite counts them.
+ */
+#ifndef MG5MI_H
+#define MG5MI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define MG_OK 0
+#define MG_EINVAL (-1)   /* invalid argument: null pointer, nevt < 0, bad enum */
+#define MG_ENOTSUP (-2)  /* precision or entry point not built for this process */
+#define MG_ENOPHASE (-3) /* sum of final-state masses >= sqrt(s) */
+#define MG_EHIP (-4)     /* HIP runtime or launch error */
+#define MG_EALIGN (-5)   /* buffer not 8-byte aligned */
+#define MG_ENOMEM (-6)   /* mg_create could not allocate its small tables */
+
+/* processes (Sec. II, Table "tab-compl"; particle order as written) */
+typedef enum {
+  MG_EEMUMU = 0, /* e+ e- -> mu+ mu-   (Fig. 1: photon and Z exchange) */
+  MG_GGTT = 1,   /* g g -> t t~ */
+  MG_GGTTG = 2,  /* g g -> t t~ g */
+  MG_GGTTGG = 3  /* g g -> t t~ g g */
+} mg_proc_t;
+
+/* arithmetic of the matrix-element engine (Sec. IV.b, single/double
+ * precision switch, refined per stage):
+ *   MG_FP64     everything in binary64
+ *   MG_FP32AMP  wavefunctions, currents, amplitudes, jamps and the colour
+ *               sum in binary32 (VALU); momenta, propagator denominators,
+ *               helicity sum and /IDEN in binary64
+ *   MG_MIXED    as MG_FP32AMP but the colour sum runs on the matrix cores
+ *               (MFMA) with FP32 accumulation */
+typedef enum { MG_FP64 = 0, MG_FP32AMP = 1, MG_MIXED = 2 } mg_prec_t;
+
+/* physics inputs; couplings are derived in mg_create (sin^2 theta_W in the
+ * G_F scheme from alpha, G_F and mZ) */
+typedef struct {
+  double sqrts;     /* partonic centre-of-mass energy [GeV] */
+  double alpha_inv; /* 1/alpha */
+  double gfermi;    /* G_F [GeV^-2] */
+  double mZ, wZ;    /* Z mass and width [GeV] */
+  double mt, wt;    /* top mass and width [GeV]; wt may be 0 */
+  double alphas;    /* strong coupling (fixed) */
+} mg_params_t;
+
+typedef struct {
+  int npar;      /* external particles */
+  int nparf;     /* final-state particles */
+  int nrnd;      /* uniforms per event = 4 * nparf */
+  int nhel;      /* helicity combinations (2^npar) */
+  int nhel_good; /* helicities kept after filtering (exactly-zero ones dropped) */
+  int ncol;      /* colour flows */
+  int ndiag;     /* Feynman diagrams (4-gluon vertex counted once) */
+  int neppM;     /* events per momentum page */
+  int neppR;     /* events per random-number page */
+  int iden;      /* spin/colour average and identical-particle factor */
+} mg_layout_t;
+
+typedef struct mg_handle mg_handle_t;
+
+/* Create a handle for one process and precision on the current HIP device.
+ * Derives couplings, uploads small tables and determines the nonzero
+ * helicities on 64 internally sampled events (synchronises the device).
+ * prm == NULL selects the defaults (sqrt(s)=1500, 1/alpha=132.5,
+ * G_F=1.16639e-5, mZ=91.188, wZ=2.441, mt=173, wt=1.49, alpha_s=0.118).
+ * Errors: MG_EINVAL, MG_ENOTSUP, MG_ENOPHASE, MG_ENOMEM, MG_EHIP. */
+int mg_create(int proc, int prec, const mg_params_t* prm, mg_handle_t** out);
+int mg_destroy(mg_handle_t* h);
+int mg_layout(const mg_handle_t* h, mg_layout_t* out);
+
+/* Uniform randoms (Sec. IV.b random-number component): Philox4x32-10 with
+ * key = seed and counter = (global event index evt_offset + i, block), so
+ * any event range is reproducible independently of how it is split.
+ * u = ((w >> 11) + 1/2) 2^-53 in (0, 1).  rnd: AoSoA, nrnd per event. */
+int mg_rng(const mg_handle_t* h, uint64_t seed, int64_t evt_offset, int64_t nevt, double* rnd,
+           void* stream);
+
+/* RAMBO phase space (Sec. IV.a/IV.b phase-space sampler; Kleiss, Stirling,
+ * Ellis 1986): rnd (AoSoA) -> mom (AoSoA, all npar particles, initial
+ * momenta along +-z) and weights wgt[nevt] (phase-space volume measure
+ * prod d^3p/(2E) delta^4, no 2pi factors, no flux).  Massive final states
+ * by Newton rescaling in FP64; a non-converged event gets a NaN weight. */
+int mg_rambo(const mg_handle_t* h, const double* rnd, int64_t nevt, double* mom, double* wgt,
+             void* stream);
+
+/* mg_rng + mg_rambo fused in one kernel; rnd_or_null == NULL keeps the
+ * uniforms in registers (never written to memory). */
+int mg_sample(const mg_handle_t* h, uint64_t seed, int64_t evt_offset, int64_t nevt,
+              double* rnd_or_null, double* mom, double* wgt, void* stream);
+
+/* Matrix elements (Sec. II, SIGMAKIN): me[i] = (1/IDEN) sum over kept
+ * helicities and all colours of |M|^2 for the momenta of event i.
+ * If both wgt_or_null and evtw_or_null are given, evtw[i] = wgt[i]*me[i]. */
+int mg_sigmakin(const mg_handle_t* h, const double* mom, int64_t nevt, double* me,
+                const double* wgt_or_null, double* evtw_or_null, void* stream);
+
+/* Per-helicity colour-summed |M|^2 (not divided by IDEN), for ALL 2^npar
+ * helicities: mehel[ihel * nevt + i].  Used for helicity filtering and
+ * tests; helicity ihel gives particle k the helicity +1 if bit (npar-1-k)
+ * of ihel is set, else -1. */
+int mg_sigmakin_hel(const mg_handle_t* h, const double* mom, int64_t nevt, double* mehel,
+                    void* stream);
+
+/* Number of non-finite entries of x[0..n) accumulated into *d_count (a
+ * device int64 the caller zeroes first). */
+int mg_count_nonfinite(const double* x, int64_t n, int64_t* d_count, void* stream);
+
+const char* mg_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MG5MI_H */

@@ -1,0 +1,212 @@
+"""Per-event |M|^2 on AMD MI355X (gfx950): thin binding over libmg5mi.so.
+
+Only argument marshalling lives here: torch supplies device memory and the
+current HIP stream, and every step of the path (random numbers, RAMBO,
+helicity amplitudes, colour and helicity sums) runs in the library's HIP
+kernels through the C ABI of include/mg5mi.h.  There is no CPU fallback: if
+the library is missing, construction raises.
+"""
+import ctypes
+import os
+
+import torch
+
+__all__ = ['MEEngine', 'MEWeight', 'PROCESSES', 'PRECISIONS', 'lib', 'library_path']
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+PROCESSES = {'eemumu': 0, 'ggtt': 1, 'ggttg': 2, 'ggttgg': 3}
+PRECISIONS = {'fp64': 0, 'fp32amp': 1, 'mixed': 2}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [('sqrts', ctypes.c_double), ('alpha_inv', ctypes.c_double),
+                ('gfermi', ctypes.c_double), ('mZ', ctypes.c_double), ('wZ', ctypes.c_double),
+                ('mt', ctypes.c_double), ('wt', ctypes.c_double), ('alphas', ctypes.c_double)]
+
+
+DEFAULT_PARAMS = dict(sqrts=1500.0, alpha_inv=132.5, gfermi=1.16639e-5, mZ=91.188, wZ=2.441,
+                      mt=173.0, wt=1.49, alphas=0.118)
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in
+                ('npar', 'nparf', 'nrnd', 'nhel', 'nhel_good', 'ncol', 'ndiag', 'neppM', 'neppR',
+                 'iden')]
+
+
+_LIB = None
+
+
+def library_path():
+    return os.path.join(_HERE, 'libmg5mi.so')
+
+
+def lib():
+    """Load libmg5mi.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_2106_12631_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i64, u64, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
+    sigs = {
+        'mg_create': [ci, ci, ctypes.POINTER(Params), ctypes.POINTER(vp)],
+        'mg_destroy': [vp],
+        'mg_layout': [vp, ctypes.POINTER(Layout)],
+        'mg_rng': [vp, u64, i64, i64, vp, vp],
+        'mg_rambo': [vp, vp, i64, vp, vp, vp],
+        'mg_sample': [vp, u64, i64, i64, vp, vp, vp, vp],
+        'mg_sigmakin': [vp, vp, i64, vp, vp, vp, vp],
+        'mg_sigmakin_hel': [vp, vp, i64, vp, vp],
+        'mg_count_nonfinite': [vp, i64, vp, vp],
+    }
+    for name, args in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ci
+    L.mg_strerror.argtypes = [ci]
+    L.mg_strerror.restype = ctypes.c_char_p
+    _LIB = L
+    return L
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"{what} failed: {lib().mg_strerror(rc).decode()} ({rc})")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class MEEngine:
+    """One process at one precision on one device (wraps an mg_handle_t)."""
+
+    def __init__(self, process, precision='fp64', params=None, device='cuda'):
+        self.process = process
+        self.precision = precision
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device('cuda', torch.cuda.current_device())
+        prm = dict(DEFAULT_PARAMS)
+        prm.update(params or {})
+        self.params = prm
+        L = lib()
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.mg_create(PROCESSES[process], PRECISIONS[precision],
+                               ctypes.byref(Params(**prm)), ctypes.byref(h)), 'mg_create')
+        self._h = h
+        lay = Layout()
+        _check(L.mg_layout(h, ctypes.byref(lay)), 'mg_layout')
+        self.layout = lay
+
+    def __del__(self):
+        h = getattr(self, '_h', None)
+        if h is not None and _LIB is not None:
+            _LIB.mg_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------ buffers
+    def _pages(self, nevt, nepp):
+        return (nevt + nepp - 1) // nepp
+
+    def empty_mom(self, nevt):
+        lay = self.layout
+        return torch.empty(self._pages(nevt, lay.neppM) * lay.npar * 4 * lay.neppM,
+                           dtype=torch.float64, device=self.device)
+
+    def empty_rnd(self, nevt):
+        lay = self.layout
+        return torch.empty(self._pages(nevt, lay.neppR) * lay.nrnd * lay.neppR,
+                           dtype=torch.float64, device=self.device)
+
+    # ------------------------------------------------------------ layout views
+    def mom_events(self, mom, nevt):
+        """AoSoA momenta -> (nevt, npar, 4) tensor (copy)."""
+        lay = self.layout
+        v = mom.view(-1, lay.npar, 4, lay.neppM).permute(0, 3, 1, 2)
+        return v.reshape(-1, lay.npar, 4)[:nevt].contiguous()
+
+    def events_mom(self, p):
+        """(nevt, npar, 4) tensor -> AoSoA momenta on this device (padded page)."""
+        lay = self.layout
+        nevt = p.shape[0]
+        npg = self._pages(nevt, lay.neppM)
+        buf = torch.zeros(npg * lay.neppM, lay.npar, 4, dtype=torch.float64, device=self.device)
+        buf[:nevt] = p.to(self.device, torch.float64)
+        return buf.view(npg, lay.neppM, lay.npar, 4).permute(0, 2, 3, 1).contiguous().view(-1)
+
+    def rnd_events(self, rnd, nevt):
+        lay = self.layout
+        v = rnd.view(-1, lay.nrnd, lay.neppR).permute(0, 2, 1)
+        return v.reshape(-1, lay.nrnd)[:nevt].contiguous()
+
+    def events_rnd(self, r):
+        lay = self.layout
+        nevt = r.shape[0]
+        npg = self._pages(nevt, lay.neppR)
+        buf = torch.full((npg * lay.neppR, lay.nrnd), 0.5, dtype=torch.float64, device=self.device)
+        buf[:nevt] = r.to(self.device, torch.float64)
+        return buf.view(npg, lay.neppR, lay.nrnd).permute(0, 2, 1).contiguous().view(-1)
+
+    # ------------------------------------------------------------ the path
+    def rng(self, seed, nevt, offset=0, out=None):
+        rnd = self.empty_rnd(nevt) if out is None else out
+        _check(lib().mg_rng(self._h, seed, offset, nevt, _ptr(rnd), _stream(self.device)), 'mg_rng')
+        return rnd
+
+    def rambo(self, rnd, nevt, mom=None, wgt=None):
+        mom = self.empty_mom(nevt) if mom is None else mom
+        wgt = torch.empty(nevt, dtype=torch.float64, device=self.device) if wgt is None else wgt
+        _check(lib().mg_rambo(self._h, _ptr(rnd), nevt, _ptr(mom), _ptr(wgt),
+                              _stream(self.device)), 'mg_rambo')
+        return mom, wgt
+
+    def sample(self, seed, nevt, offset=0, keep_rnd=False, mom=None, wgt=None):
+        rnd = self.empty_rnd(nevt) if keep_rnd else None
+        mom = self.empty_mom(nevt) if mom is None else mom
+        wgt = torch.empty(nevt, dtype=torch.float64, device=self.device) if wgt is None else wgt
+        _check(lib().mg_sample(self._h, seed, offset, nevt, _ptr(rnd), _ptr(mom), _ptr(wgt),
+                               _stream(self.device)), 'mg_sample')
+        return rnd, mom, wgt
+
+    def sigmakin(self, mom, nevt, wgt=None, me=None, evtw=None):
+        me = torch.empty(nevt, dtype=torch.float64, device=self.device) if me is None else me
+        if wgt is not None and evtw is None:
+            evtw = torch.empty(nevt, dtype=torch.float64, device=self.device)
+        _check(lib().mg_sigmakin(self._h, _ptr(mom), nevt, _ptr(me), _ptr(wgt), _ptr(evtw),
+                                 _stream(self.device)), 'mg_sigmakin')
+        return me if wgt is None else (me, evtw)
+
+    def sigmakin_hel(self, mom, nevt):
+        out = torch.empty(self.layout.nhel, nevt, dtype=torch.float64, device=self.device)
+        _check(lib().mg_sigmakin_hel(self._h, _ptr(mom), nevt, _ptr(out), _stream(self.device)),
+               'mg_sigmakin_hel')
+        return out
+
+    def count_nonfinite(self, x):
+        cnt = torch.zeros(1, dtype=torch.int64, device=self.device)
+        _check(lib().mg_count_nonfinite(_ptr(x), x.numel(), _ptr(cnt), _stream(self.device)),
+               'mg_count_nonfinite')
+        return int(cnt.item())
+
+
+class MEWeight(torch.autograd.Function):
+    """Placeholder name for the differentiable event weight (adjoint kernel)."""
+
+    @staticmethod
+    def forward(ctx, *args):
+        raise NotImplementedError("the adjoint kernel is not built yet")

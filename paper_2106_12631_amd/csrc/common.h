@@ -1,0 +1,40 @@
+// Shared device/host definitions of the gfx950 |M|^2 library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "helas.h"
+
+namespace mg {
+
+// AoSoA page sizes (Sec. IV.b "AOSOA"): 64 events per page, so one wave64
+// reads one (particle, component) row of a momentum page as 512 contiguous
+// bytes -- a fully coalesced load.
+constexpr int NEPPM = 64;
+constexpr int NEPPR = 64;
+
+// Couplings and masses handed to the kernels by value (Sec. IV.c keeps
+// physics parameters in constant memory; a kernel-argument struct lets two
+// handles with different parameters coexist).
+template <typename T>
+struct Couplings {
+  T gs, gs2;        // strong coupling and its square
+  T cqed;           // photon-lepton coupling -e Q
+  T czl, czr;       // Z-lepton chiral couplings
+  double mt, wt;    // top mass and width
+  double mz, wz;    // Z mass and width
+};
+
+struct HelList {
+  int n;
+  uint8_t code[64];
+};
+
+__host__ __device__ inline int64_t aosoa_mom(int64_t ievt, int ipar, int mu, int npar) {
+  return ((ievt / NEPPM) * npar + ipar) * 4 * NEPPM + (int64_t)mu * NEPPM + (ievt % NEPPM);
+}
+__host__ __device__ inline int64_t aosoa_rnd(int64_t ievt, int irnd, int nrnd) {
+  return ((ievt / NEPPR) * nrnd + irnd) * NEPPR + (ievt % NEPPR);
+}
+
+}  // namespace mg

@@ -1,0 +1,386 @@
+// Device routines of the helicity-amplitude method for gfx950.
+//
+// The paper computes each matrix element with three kinds of routines used
+// in sequence (Sec. II, Fig. 1): "external particle" wavefunctions from a
+// momentum and a helicity, "internal particle" off-shell currents at a
+// vertex with one unknown leg, and "amplitude" routines at a vertex whose
+// legs are all known.  These are written here from the Feynman rules in the
+// chiral (Weyl) representation, where gamma^mu = [[0, s^mu], [sb^mu, 0]] with
+// s^mu = (1, sigma), sb^mu = (1, -sigma), so that every gamma-matrix product
+// reduces to 2x2 blocks:
+//
+//   spinor     (L0, L1, R0, R1): upper = left-handed
+//   vertex     i gamma^mu (cL P_L + cR P_R)   (gluon: cL = cR = g_s, colour
+//              factor T^a handled by the generated code)
+//   g g g      g_s [g^{mu nu}(k1-k2)^rho + g^{nu rho}(k2-k3)^mu + g^{rho mu}(k3-k1)^nu]
+//   g g g g    -i g_s^2 x one of three Lorentz structures (one per f f term)
+//   propagators  vector -i g/K^2 (massless) or -i (g - K K/M^2)/(K^2 - M^2 + i M W),
+//                fermion i (P-slash + m)/(P^2 - m^2 + i m w)
+//
+// Momenta are always FP64 (kin = momentum flowing into the diagram); the
+// amplitude type T is double (FP64 path) or float (mixed path).  Every
+// momentum-only quantity -- square roots of the external momenta and the
+// propagator denominators -- is formed in FP64 and rounded to T afterwards.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mg {
+
+template <typename T>
+struct cx {
+  T r, i;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.r, -a.i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+template <typename T>
+__device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.i, a.r}; }
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.r, -a.i}; }
+
+// 1 / (re + i im) formed in FP64, rounded to T
+template <typename T>
+__device__ __forceinline__ cx<T> inv_den(double re, double im) {
+  const double n = 1.0 / (re * re + im * im);
+  return cx<T>{(T)(re * n), (T)(-im * n)};
+}
+
+// ---------------------------------------------------------------------------
+// external wavefunctions
+// ---------------------------------------------------------------------------
+
+// Polarisation vector eps^mu(p, lam) of a massless vector boson; conj = true
+// gives eps* (outgoing).  eps = (-lam e1 - i e2)/sqrt2 with
+// e1 = (0, cth cph, cth sph, -sth), e2 = (0, -sph, cph, 0); phi = 0 when pT = 0.
+template <typename T>
+__device__ __forceinline__ void ext_vector(const double p[4], int lam, bool conjugate, cx<T> w[4]) {
+  const double kt2 = p[1] * p[1] + p[2] * p[2];
+  const double K = sqrt(kt2 + p[3] * p[3]);
+  const double kt = sqrt(kt2);
+  const double cth = p[3] / K, sth = kt / K;
+  double cph = 1.0, sph = 0.0;
+  if (kt > 0.0) {
+    cph = p[1] / kt;
+    sph = p[2] / kt;
+  }
+  const double r2 = 0.70710678118654752440;
+  const double a = -lam * r2;             // coefficient of e1 (real part)
+  const double b = conjugate ? r2 : -r2;  // coefficient of e2 (imaginary part)
+  w[0] = cx<T>{(T)0, (T)0};
+  w[1] = cx<T>{(T)(a * cth * cph), (T)(b * -sph)};
+  w[2] = cx<T>{(T)(a * cth * sph), (T)(b * cph)};
+  w[3] = cx<T>{(T)(a * -sth), (T)0};
+}
+
+// Two-component helicity state for the direction of p.  P + pz is formed as
+// pT^2 / (P - pz) when pz < 0 to avoid cancellation; along -z the limit
+// theta = pi, phi = 0 gives chi+ = (0, 1), chi- = (-1, 0).
+struct chi_pair {
+  double pr, pi_;  // chi component with the phase (px + i py)/nrm
+  double a;        // real component (P + pz)/nrm
+  bool mz;         // direction is -z
+};
+
+__device__ __forceinline__ void helicity_chi(const double p[4], int lam, double& c0r, double& c0i,
+                                             double& c1r, double& c1i) {
+  const double pt2 = p[1] * p[1] + p[2] * p[2];
+  const double P = sqrt(pt2 + p[3] * p[3]);
+  double ppz;
+  if (p[3] >= 0.0) {
+    ppz = P + p[3];
+  } else {
+    const double d = P - p[3];
+    ppz = d > 0.0 ? pt2 / d : 0.0;
+  }
+  if (!(ppz > 0.0)) {  // along -z
+    if (lam > 0) { c0r = 0; c0i = 0; c1r = 1; c1i = 0; }
+    else { c0r = -1; c0i = 0; c1r = 0; c1i = 0; }
+    return;
+  }
+  const double nrm = 1.0 / sqrt(2.0 * P * ppz);
+  if (lam > 0) {  // (P + pz, px + i py) / nrm
+    c0r = ppz * nrm; c0i = 0;
+    c1r = p[1] * nrm; c1i = p[2] * nrm;
+  } else {        // (-(px - i py), P + pz) / nrm
+    c0r = -p[1] * nrm; c0i = p[2] * nrm;
+    c1r = ppz * nrm; c1i = 0;
+  }
+}
+
+// (sqrt(E - lam P), sqrt(E + lam P)); E - P = m^2 / (E + P), exactly 0 if m = 0
+__device__ __forceinline__ void omegas(const double p[4], double m, int lam, double& wm, double& wp) {
+  const double P = sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+  const double epp = p[0] + P;
+  const double emp = (m == 0.0) ? 0.0 : m * m / epp;
+  const double se = sqrt(emp), sp = sqrt(epp);
+  if (lam > 0) { wm = se; wp = sp; } else { wm = sp; wp = se; }
+}
+
+// u(p, lam) = (sqrt(E - lam P) chi_lam, sqrt(E + lam P) chi_lam); bar = u^dagger gamma^0
+template <typename T>
+__device__ __forceinline__ void ext_u(const double p[4], double m, int lam, bool barred, cx<T> w[4]) {
+  double wm, wp, c0r, c0i, c1r, c1i;
+  omegas(p, m, lam, wm, wp);
+  helicity_chi(p, lam, c0r, c0i, c1r, c1i);
+  const double s = barred ? -1.0 : 1.0;  // conjugation flips the imaginary parts
+  const cx<T> L0{(T)(wm * c0r), (T)(s * wm * c0i)}, L1{(T)(wm * c1r), (T)(s * wm * c1i)};
+  const cx<T> R0{(T)(wp * c0r), (T)(s * wp * c0i)}, R1{(T)(wp * c1r), (T)(s * wp * c1i)};
+  if (barred) { w[0] = R0; w[1] = R1; w[2] = L0; w[3] = L1; }  // gamma^0 swaps the blocks
+  else { w[0] = L0; w[1] = L1; w[2] = R0; w[3] = R1; }
+}
+
+// v(p, lam) = (sqrt(E + lam P) chi_-lam, -sqrt(E - lam P) chi_-lam)
+template <typename T>
+__device__ __forceinline__ void ext_v(const double p[4], double m, int lam, bool barred, cx<T> w[4]) {
+  double wm, wp, c0r, c0i, c1r, c1i;
+  omegas(p, m, lam, wm, wp);
+  helicity_chi(p, -lam, c0r, c0i, c1r, c1i);
+  const double s = barred ? -1.0 : 1.0;
+  const cx<T> L0{(T)(wp * c0r), (T)(s * wp * c0i)}, L1{(T)(wp * c1r), (T)(s * wp * c1i)};
+  const cx<T> R0{(T)(-wm * c0r), (T)(-s * wm * c0i)}, R1{(T)(-wm * c1r), (T)(-s * wm * c1i)};
+  if (barred) { w[0] = R0; w[1] = R1; w[2] = L0; w[3] = L1; }
+  else { w[0] = L0; w[1] = L1; w[2] = R0; w[3] = R1; }
+}
+
+// ---------------------------------------------------------------------------
+// 2x2 blocks of V-slash for a complex vector V (contravariant components)
+//   sV  = s^mu V_mu  = [[V0 - V3, -(V1 - i V2)], [-(V1 + i V2), V0 + V3]]
+//   sbV = sb^mu V_mu = [[V0 + V3,   V1 - i V2 ], [  V1 + i V2,  V0 - V3]]
+// ---------------------------------------------------------------------------
+template <typename T>
+struct blk {
+  cx<T> a, b, c, d;  // [[a, b], [c, d]]
+};
+
+template <typename T>
+__device__ __forceinline__ void slash_blocks(const cx<T> V[4], blk<T>& s, blk<T>& sb) {
+  const cx<T> v0p3 = V[0] + V[3], v0m3 = V[0] - V[3];
+  const cx<T> v1mi2 = V[1] - times_i(V[2]), v1pi2 = V[1] + times_i(V[2]);
+  s = blk<T>{v0m3, -v1mi2, -v1pi2, v0p3};
+  sb = blk<T>{v0p3, v1mi2, v1pi2, v0m3};
+}
+
+// column: M x
+template <typename T>
+__device__ __forceinline__ void mcol(const blk<T>& m, cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
+  y0 = m.a * x0 + m.b * x1;
+  y1 = m.c * x0 + m.d * x1;
+}
+// row: x M
+template <typename T>
+__device__ __forceinline__ void mrow(const blk<T>& m, cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
+  y0 = x0 * m.a + x1 * m.c;
+  y1 = x0 * m.b + x1 * m.d;
+}
+
+// real momentum blocks sK = s.K, sbK = sb.K
+struct rblk {
+  double k0p3, k0m3, k1, k2;
+};
+
+// column: (s.K) x with s.K = [[K0-K3, -(K1 - i K2)], [-(K1 + i K2), K0+K3]]
+template <typename T>
+__device__ __forceinline__ void sK_col(const T K[4], cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
+  const cx<T> m01{-K[1], K[2]}, m10{-K[1], -K[2]};
+  y0 = (K[0] - K[3]) * x0 + m01 * x1;
+  y1 = m10 * x0 + (K[0] + K[3]) * x1;
+}
+// column: (sb.K) x with sb.K = [[K0+K3, K1 - i K2], [K1 + i K2, K0-K3]]
+template <typename T>
+__device__ __forceinline__ void sbK_col(const T K[4], cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
+  const cx<T> m01{K[1], -K[2]}, m10{K[1], K[2]};
+  y0 = (K[0] + K[3]) * x0 + m01 * x1;
+  y1 = m10 * x0 + (K[0] - K[3]) * x1;
+}
+// row: x (s.K)
+template <typename T>
+__device__ __forceinline__ void sK_row(const T K[4], cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
+  const cx<T> m01{-K[1], K[2]}, m10{-K[1], -K[2]};
+  y0 = (K[0] - K[3]) * x0 + x1 * m10;
+  y1 = x0 * m01 + (K[0] + K[3]) * x1;
+}
+// row: x (sb.K)
+template <typename T>
+__device__ __forceinline__ void sbK_row(const T K[4], cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
+  const cx<T> m01{K[1], -K[2]}, m10{K[1], K[2]};
+  y0 = (K[0] + K[3]) * x0 + x1 * m10;
+  y1 = x0 * m01 + (K[0] - K[3]) * x1;
+}
+
+template <typename T>
+__device__ __forceinline__ void to_T(const double K[4], T k[4]) {
+  k[0] = (T)K[0]; k[1] = (T)K[1]; k[2] = (T)K[2]; k[3] = (T)K[3];
+}
+
+__device__ __forceinline__ double msq(const double K[4]) {
+  return K[0] * K[0] - K[1] * K[1] - K[2] * K[2] - K[3] * K[3];
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> mdot(const cx<T> a[4], const cx<T> b[4]) {
+  return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+}
+template <typename T>
+__device__ __forceinline__ cx<T> mdot(const T k[4], const cx<T> b[4]) {
+  return k[0] * b[0] - k[1] * b[1] - k[2] * b[2] - k[3] * b[3];
+}
+
+// ---------------------------------------------------------------------------
+// f f V : amplitude, vector current, flow-in and flow-out fermion currents
+// ---------------------------------------------------------------------------
+
+// bilinear J^mu = F gamma^mu (cL P_L + cR P_R) G for row F, column G
+template <typename T>
+__device__ __forceinline__ void ffv_bilinear(const cx<T> F[4], const cx<T> G[4], T cL, T cR,
+                                             cx<T> J[4]) {
+  // a = F_L s^mu G_R, b = F_R sb^mu G_L (sb^mu = (1, -sigma))
+  const cx<T> a00 = F[0] * G[2], a11 = F[1] * G[3], a01 = F[0] * G[3], a10 = F[1] * G[2];
+  const cx<T> b00 = F[2] * G[0], b11 = F[3] * G[1], b01 = F[2] * G[1], b10 = F[3] * G[0];
+  // s^mu bilinear x^T s^mu y: (x0y0 + x1y1, x0y1 + x1y0, i(x1y0 - x0y1), x0y0 - x1y1)
+  J[0] = cR * (a00 + a11) + cL * (b00 + b11);
+  J[1] = cR * (a01 + a10) - cL * (b01 + b10);
+  J[2] = cR * times_i(a10 - a01) - cL * times_i(b10 - b01);
+  J[3] = cR * (a00 - a11) - cL * (b00 - b11);
+}
+
+// amplitude i F V-slash (cL P_L + cR P_R) G
+template <typename T>
+__device__ __forceinline__ cx<T> ffv_amp(const cx<T> F[4], const cx<T> V[4], const cx<T> G[4], T cL,
+                                         T cR) {
+  cx<T> J[4];
+  ffv_bilinear(F, G, cL, cR, J);
+  return times_i(mdot(J, V));
+}
+
+// vector current from F, G through a massless (photon, gluon) propagator:
+// (-i/K^2) i J^mu = J^mu / K^2
+template <typename T>
+__device__ __forceinline__ void ffv_cur_v0(const cx<T> F[4], const cx<T> G[4], T cL, T cR,
+                                           const double K[4], cx<T> out[4]) {
+  cx<T> J[4];
+  ffv_bilinear(F, G, cL, cR, J);
+  const T rk = (T)(1.0 / msq(K));
+  for (int m = 0; m < 4; ++m) out[m] = rk * J[m];
+}
+
+// vector current through a massive propagator in unitary gauge:
+// (J - K (K.J)/M^2) / (K^2 - M^2 + i M W)
+template <typename T>
+__device__ __forceinline__ void ffv_cur_vm(const cx<T> F[4], const cx<T> G[4], T cL, T cR,
+                                           const double K[4], double M, double W, cx<T> out[4]) {
+  cx<T> J[4];
+  ffv_bilinear(F, G, cL, cR, J);
+  T k[4];
+  to_T(K, k);
+  const cx<T> kj = (T)(1.0 / (M * M)) * mdot(k, J);
+  const cx<T> d = inv_den<T>(msq(K) - M * M, M * W);
+  for (int m = 0; m < 4; ++m) out[m] = d * (J[m] - k[m] * kj);
+}
+
+// flow-in fermion current: i(K-slash + m)/D * i V-slash (cL P_L + cR P_R) G
+template <typename T>
+__device__ __forceinline__ void ffv_cur_fin(const cx<T> V[4], const cx<T> G[4], T cL, T cR,
+                                            const double K[4], double m, double w, cx<T> out[4]) {
+  blk<T> s, sb;
+  slash_blocks(V, s, sb);
+  // phi = V-slash (cL G_L, cR G_R) = (sV cR G_R, sbV cL G_L)
+  cx<T> f0, f1, f2, f3;
+  mcol(s, cR * G[2], cR * G[3], f0, f1);
+  mcol(sb, cL * G[0], cL * G[1], f2, f3);
+  // (K-slash + m) phi = (sK phi_R + m phi_L, sbK phi_L + m phi_R)
+  T k[4];
+  to_T(K, k);
+  const T mm = (T)m;
+  cx<T> y0, y1, y2, y3;
+  sK_col(k, f2, f3, y0, y1);
+  sbK_col(k, f0, f1, y2, y3);
+  const cx<T> d = -inv_den<T>(msq(K) - m * m, m * w);  // i * i = -1
+  out[0] = d * (y0 + mm * f0);
+  out[1] = d * (y1 + mm * f1);
+  out[2] = d * (y2 + mm * f2);
+  out[3] = d * (y3 + mm * f3);
+}
+
+// flow-out fermion current: F i V-slash (cL P_L + cR P_R) * i(-K-slash + m)/D
+template <typename T>
+__device__ __forceinline__ void ffv_cur_fout(const cx<T> F[4], const cx<T> V[4], T cL, T cR,
+                                             const double K[4], double m, double w, cx<T> out[4]) {
+  blk<T> s, sb;
+  slash_blocks(V, s, sb);
+  // row phi = F [[0, sV cR], [sbV cL, 0]] = (F_R sbV cL, F_L sV cR)
+  cx<T> f0, f1, f2, f3;
+  mrow(sb, F[2], F[3], f0, f1);
+  mrow(s, F[0], F[1], f2, f3);
+  f0 = cL * f0; f1 = cL * f1; f2 = cR * f2; f3 = cR * f3;
+  // phi (-K-slash + m) = (m phi_L - phi_R sbK, -phi_L sK + m phi_R)
+  T k[4];
+  to_T(K, k);
+  const T mm = (T)m;
+  cx<T> y0, y1, y2, y3;
+  sbK_row(k, f2, f3, y0, y1);
+  sK_row(k, f0, f1, y2, y3);
+  const cx<T> d = -inv_den<T>(msq(K) - m * m, m * w);
+  out[0] = d * (mm * f0 - y0);
+  out[1] = d * (mm * f1 - y1);
+  out[2] = d * (mm * f2 - y2);
+  out[3] = d * (mm * f3 - y3);
+}
+
+// ---------------------------------------------------------------------------
+// gluon self-couplings (colour handled by the generated code)
+// ---------------------------------------------------------------------------
+
+// three-gluon current with legs (out, A, B), colour f^{out A B}:
+// (-i/K^2) g [A (-(2kA + kB).B) + (A.B)(kA - kB) + B ((kA + 2kB).A)]
+template <typename T>
+__device__ __forceinline__ void vvv_cur(const cx<T> A[4], const double KA[4], const cx<T> B[4],
+                                        const double KB[4], T g, cx<T> out[4]) {
+  double qa[4], qb[4], dk[4], K[4];
+  for (int m = 0; m < 4; ++m) {
+    qa[m] = -(2.0 * KA[m] + KB[m]);
+    qb[m] = KA[m] + 2.0 * KB[m];
+    dk[m] = KA[m] - KB[m];
+    K[m] = KA[m] + KB[m];
+  }
+  T tqa[4], tqb[4], tdk[4];
+  to_T(qa, tqa);
+  to_T(qb, tqb);
+  to_T(dk, tdk);
+  const cx<T> ca = mdot(tqa, B), cb = mdot(tqb, A), ab = mdot(A, B);
+  // (-i g / K^2) [...]
+  const cx<T> pre{(T)0, (T)(-1.0 / msq(K)) * g};
+  for (int m = 0; m < 4; ++m) out[m] = pre * (A[m] * ca + tdk[m] * ab + B[m] * cb);
+}
+
+// four-gluon current, structure s (1, 2, 3), legs (out, X, Y, Z):
+//   s=1: Y (X.Z) - Z (X.Y)   s=2: X (Y.Z) - Z (X.Y)   s=3: X (Y.Z) - Y (X.Z)
+// times (-i g^2)(-i/K^2) = -g^2/K^2
+template <int S, typename T>
+__device__ __forceinline__ void vvvv_cur(const cx<T> X[4], const cx<T> Y[4], const cx<T> Z[4],
+                                         const double K[4], T g2, cx<T> out[4]) {
+  const T pre = (T)(-1.0 / msq(K)) * g2;
+  if (S == 1) {
+    const cx<T> xz = pre * mdot(X, Z), xy = pre * mdot(X, Y);
+    for (int m = 0; m < 4; ++m) out[m] = Y[m] * xz - Z[m] * xy;
+  } else if (S == 2) {
+    const cx<T> yz = pre * mdot(Y, Z), xy = pre * mdot(X, Y);
+    for (int m = 0; m < 4; ++m) out[m] = X[m] * yz - Z[m] * xy;
+  } else {
+    const cx<T> yz = pre * mdot(Y, Z), xz = pre * mdot(X, Z);
+    for (int m = 0; m < 4; ++m) out[m] = X[m] * yz - Y[m] * xz;
+  }
+}
+
+}  // namespace mg

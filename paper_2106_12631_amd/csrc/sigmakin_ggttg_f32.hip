@@ -1,0 +1,27 @@
+// SIGMAKIN for ggttg with float amplitudes: the generated colour-flow amplitudes
+// and colour sum wrapped for the kernel of sigmakin_impl.h.
+#include "sigmakin_impl.h"
+
+namespace mg {
+#include "generated/ggttg.inc"
+
+struct P_ggttg {
+  static constexpr int NPAR = gen_ggttg::NPAR;
+  static constexpr int NCOL = gen_ggttg::NCOL;
+  template <typename T>
+  __device__ static __forceinline__ void jamps(const double (&p)[NPAR][4], unsigned h,
+                                               const Couplings<T>& c, cx<T> (&J)[NCOL]) {
+    gen_ggttg::jamps<T>(p, h, c, J);
+  }
+  template <typename T>
+  __device__ static __forceinline__ T colour_sum(const cx<T> (&J)[NCOL]) {
+    return gen_ggttg::colour_sum<T>(J);
+  }
+};
+
+int launch_sigmakin_ggttg_f32(const MeArgs& a, const double* mom, int64_t nevt, double* me,
+                              const double* wgt, double* evtw, double* mehel, hipStream_t s) {
+  return sigmakin_launch<P_ggttg, float, 256>(a, a.c32, mom, nevt, me, wgt, evtw, mehel, s);
+}
+
+}  // namespace mg

@@ -1,0 +1,27 @@
+// SIGMAKIN for ggttgg with float amplitudes: the generated colour-flow amplitudes
+// and colour sum wrapped for the kernel of sigmakin_impl.h.
+#include "sigmakin_impl.h"
+
+namespace mg {
+#include "generated/ggttgg.inc"
+
+struct P_ggttgg {
+  static constexpr int NPAR = gen_ggttgg::NPAR;
+  static constexpr int NCOL = gen_ggttgg::NCOL;
+  template <typename T>
+  __device__ static __forceinline__ void jamps(const double (&p)[NPAR][4], unsigned h,
+                                               const Couplings<T>& c, cx<T> (&J)[NCOL]) {
+    gen_ggttgg::jamps<T>(p, h, c, J);
+  }
+  template <typename T>
+  __device__ static __forceinline__ T colour_sum(const cx<T> (&J)[NCOL]) {
+    return gen_ggttgg::colour_sum<T>(J);
+  }
+};
+
+int launch_sigmakin_ggttgg_f32(const MeArgs& a, const double* mom, int64_t nevt, double* me,
+                              const double* wgt, double* evtw, double* mehel, hipStream_t s) {
+  return sigmakin_launch<P_ggttgg, float, 64>(a, a.c32, mom, nevt, me, wgt, evtw, mehel, s);
+}
+
+}  // namespace mg

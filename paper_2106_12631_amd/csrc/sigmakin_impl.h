@@ -1,0 +1,70 @@
+// SIGMAKIN kernels for one process (Sec. II, Sec. IV.b): one event per lane,
+// the loop over the kept helicities inside the lane; per helicity the
+// generated straight-line code builds the colour-flow amplitudes and the
+// colour sum gives the helicity's |M|^2, accumulated in FP64.
+#pragma once
+#include "common.h"
+#include "internal.h"
+
+namespace mg {
+
+template <class P>
+__device__ __forceinline__ void load_event(const double* __restrict__ mom, int64_t i,
+                                           double (&p)[P::NPAR][4]) {
+#pragma unroll
+  for (int ip = 0; ip < P::NPAR; ++ip)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) p[ip][m] = mom[aosoa_mom(i, ip, m, P::NPAR)];
+}
+
+// me[i] = inv_iden * sum_k |M|^2(helicity hl.code[k]); with mehel != null the
+// per-helicity values are also stored at mehel[hl.code[k] * nevt + i].
+template <class P, typename T, int BS>
+__global__ void __launch_bounds__(BS)
+    sigmakin_kernel(const double* __restrict__ mom, int64_t nevt, double* __restrict__ me,
+                    const double* __restrict__ wgt, double* __restrict__ evtw,
+                    double* __restrict__ mehel, HelList hl, Couplings<T> c, double inv_iden) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= nevt) return;
+  double p[P::NPAR][4];
+  load_event<P>(mom, i, p);
+  double acc = 0.0;
+#pragma nounroll
+  for (int k = 0; k < hl.n; ++k) {
+    // The momenta are passed through an empty asm each iteration so that no
+    // helicity-independent subexpression (momentum sums, propagator
+    // denominators) is hoisted out of the loop: recomputing them is cheap,
+    // keeping them live across the loop is not.
+    double q[P::NPAR][4];
+#pragma unroll
+    for (int ip = 0; ip < P::NPAR; ++ip)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        q[ip][m] = p[ip][m];
+        asm volatile("" : "+v"(q[ip][m]));
+      }
+    cx<T> J[P::NCOL];
+    P::template jamps<T>(q, hl.code[k], c, J);
+    const double v = (double)P::template colour_sum<T>(J);
+    if (mehel) mehel[(int64_t)hl.code[k] * nevt + i] = v;
+    acc += v;
+  }
+  const double m = acc * inv_iden;
+  if (me) me[i] = m;
+  if (evtw) evtw[i] = m * wgt[i];
+}
+
+template <class P, typename T, int BS>
+int sigmakin_launch(const MeArgs& a, const Couplings<T>& c, const double* mom, int64_t nevt,
+                    double* me, const double* wgt, double* evtw, double* mehel, hipStream_t s) {
+  const unsigned g = (unsigned)((nevt + BS - 1) / BS);
+  HelList hl = a.hel;
+  if (mehel) {  // every helicity
+    hl.n = 1 << P::NPAR;
+    for (int k = 0; k < hl.n; ++k) hl.code[k] = (uint8_t)k;
+  }
+  sigmakin_kernel<P, T, BS><<<g, BS, 0, s>>>(mom, nevt, me, wgt, evtw, mehel, hl, c, a.inv_iden);
+  return 0;
+}
+
+}  // namespace mg
