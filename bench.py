@@ -93,7 +93,19 @@ def main():
     ap.add_argument('--precisions', default='fp64,fp32amp')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--cpu-events-per-worker', type=int, default=96)
+    ap.add_argument('--copy-calibration', action='store_true',
+                    help='only run a plain 1 GiB device-to-device copy (HBM counter calibration)')
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = 1 << 27
+        src = torch.ones(n, dtype=torch.float64, device='cuda')
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 8, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(events shard trivially across GPUs, see the design notes)", file=sys.stderr)

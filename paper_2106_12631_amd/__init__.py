@@ -38,7 +38,8 @@ _LIB = None
 
 
 def library_path():
-    return os.path.join(_HERE, 'libmg5mi.so')
+    """The in-tree library; MG5MI_LIBRARY may name another build of it."""
+    return os.environ.get('MG5MI_LIBRARY') or os.path.join(_HERE, 'libmg5mi.so')
 
 
 def lib():

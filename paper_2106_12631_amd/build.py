@@ -29,7 +29,7 @@ def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith('.hip'))
 
 
-def build(force=True, verbose=True, extra_flags=()):
+def build(force=True, verbose=True, extra_flags=(), output=None):
     sys.path.insert(0, os.path.dirname(HERE))
     from paper_2106_12631_amd.gen import emit
     emit.write_all(os.path.join(CSRC, 'generated'))
@@ -55,12 +55,13 @@ def build(force=True, verbose=True, extra_flags=()):
             print(f"[build] {src}:\n" + "\n".join(lines[-20:]), file=sys.stderr)
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
-    tmp = LIB + '.tmp'
+    lib = output or LIB
+    tmp = lib + '.tmp'
     subprocess.check_call([HIPCC, '--offload-arch=gfx950', '-shared', '-fPIC', '-o', tmp, *objs])
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"[build] {LIB} in {time.time() - t0:.1f}s", file=sys.stderr)
-    return LIB
+        print(f"[build] {lib} in {time.time() - t0:.1f}s", file=sys.stderr)
+    return lib
 
 
 if __name__ == '__main__':

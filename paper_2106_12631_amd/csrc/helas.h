@@ -57,6 +57,26 @@ __device__ __forceinline__ cx<T> inv_den(double re, double im) {
   return cx<T>{(T)(re * n), (T)(-im * n)};
 }
 
+// Opaque copy: the compiler must assume the four components changed, so a
+// wavefunction recomputed from it is not merged with an earlier computation.
+template <typename T>
+__device__ __forceinline__ void opaque4(cx<T> (&w)[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) asm volatile("" : "+v"(w[k].r), "+v"(w[k].i));
+}
+
+// Scheduling fence between groups of amplitude terms: the momenta are made
+// opaque (so momentum sums of one group are not merged with identical ones
+// of another group and kept live in between) and the machine scheduler may
+// not move instructions across the fence.  The generated code orders its
+// work to bound the number of live wavefunctions; the fence keeps that order.
+template <int N>
+__device__ __forceinline__ void fence(double (&p)[N][4]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) asm volatile("" : "+v"(p[k][0]), "+v"(p[k][1]), "+v"(p[k][2]), "+v"(p[k][3]));
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 // ---------------------------------------------------------------------------
 // external wavefunctions
 // ---------------------------------------------------------------------------

@@ -9,7 +9,7 @@ struct P_ggtt {
   static constexpr int NPAR = gen_ggtt::NPAR;
   static constexpr int NCOL = gen_ggtt::NCOL;
   template <typename T>
-  __device__ static __forceinline__ void jamps(const double (&p)[NPAR][4], unsigned h,
+  __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<T>& c, cx<T> (&J)[NCOL]) {
     gen_ggtt::jamps<T>(p, h, c, J);
   }

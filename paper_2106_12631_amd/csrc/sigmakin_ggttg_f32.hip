@@ -9,7 +9,7 @@ struct P_ggttg {
   static constexpr int NPAR = gen_ggttg::NPAR;
   static constexpr int NCOL = gen_ggttg::NCOL;
   template <typename T>
-  __device__ static __forceinline__ void jamps(const double (&p)[NPAR][4], unsigned h,
+  __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<T>& c, cx<T> (&J)[NCOL]) {
     gen_ggttg::jamps<T>(p, h, c, J);
   }

@@ -9,7 +9,7 @@ struct P_ggttgg {
   static constexpr int NPAR = gen_ggttgg::NPAR;
   static constexpr int NCOL = gen_ggttgg::NCOL;
   template <typename T>
-  __device__ static __forceinline__ void jamps(const double (&p)[NPAR][4], unsigned h,
+  __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<T>& c, cx<T> (&J)[NCOL]) {
     gen_ggttgg::jamps<T>(p, h, c, J);
   }

@@ -26,23 +26,18 @@ __global__ void __launch_bounds__(BS)
                     double* __restrict__ mehel, HelList hl, Couplings<T> c, double inv_iden) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i >= nevt) return;
-  double p[P::NPAR][4];
-  load_event<P>(mom, i, p);
   double acc = 0.0;
 #pragma nounroll
   for (int k = 0; k < hl.n; ++k) {
-    // The momenta are passed through an empty asm each iteration so that no
-    // helicity-independent subexpression (momentum sums, propagator
-    // denominators) is hoisted out of the loop: recomputing them is cheap,
-    // keeping them live across the loop is not.
+    // The momenta are re-read (cache hits) through an event index the
+    // compiler cannot see through, so that no helicity-independent
+    // subexpression (momentum sums, propagator denominators) is hoisted out
+    // of the loop and kept live across it: recomputing them is cheap,
+    // keeping them in registers is not.
+    int64_t iq = i;
+    asm volatile("" : "+v"(iq));
     double q[P::NPAR][4];
-#pragma unroll
-    for (int ip = 0; ip < P::NPAR; ++ip)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        q[ip][m] = p[ip][m];
-        asm volatile("" : "+v"(q[ip][m]));
-      }
+    load_event<P>(mom, iq, q);
     cx<T> J[P::NCOL];
     P::template jamps<T>(q, hl.code[k], c, J);
     const double v = (double)P::template colour_sum<T>(J);

@@ -168,6 +168,7 @@ class ProcessDiagrams:
                                     lst.append(self._vvvv(s, a, b, c, S))
             self.by_subset[S] = lst
         self.diagrams = self._close(frozenset(others))
+        self._close_early()
         self._prune()
 
     def _new(self, kind, flav, legs, colour, op):
@@ -218,6 +219,29 @@ class ProcessDiagrams:
                             col = pmul(f.colour, v.colour) if v.flav == 'g' else dict(f.colour)
                             diags.append(Diagram(f, v, root, col, self._is_rep(f) and self._is_rep(v)))
         return diags
+
+    def _close_early(self):
+        """Close a diagram whose last attachment before the root is a single
+        external gluon w one vertex earlier: F' X [prop] w root becomes
+        F' X Fin(w) with Fin(w) = the root spinor after absorbing w.  The
+        same Feynman diagram (same propagators, vertices and colour factor),
+        but the four Fin(w) currents replace every fermion current that
+        carried all but one gluon."""
+        root = self.ext[self.root]
+        fins = {}
+        out = []
+        for d in self.diagrams:
+            if d.fin is root and d.vec.op[0] == 'ext' and d.fout.op[0] == 'ffv_fout':
+                fprev, x = d.fout.op[1], d.fout.op[2]
+                w = d.vec
+                if w.idx not in fins:
+                    col = pmul(w.colour, root.colour) if w.flav == 'g' else dict(root.colour)
+                    fins[w.idx] = self._new('Fin', root.flav, w.legs | root.legs, col,
+                                            ('ffv_fin', w, root))
+                out.append(Diagram(fprev, x, fins[w.idx], d.colour, d.rep))
+            else:
+                out.append(d)
+        self.diagrams = out
 
     def _is_rep(self, n):
         if n.op[0] == 'ext':

@@ -26,8 +26,212 @@ FLOPS = {
     'ffv_amp': 118, 'ffv_cur_v0': 104, 'ffv_cur_vm': 140,
     'ffv_cur_fin': 171, 'ffv_cur_fout': 171,
     'vvv_cur': 187, 'vvvv_cur': 128,
+    'ffv_bil': 88, 'amp_dot': 30,
     'jamp_acc': 2,
 }
+
+
+class Bil:
+    """Shared bilinear F gamma^mu (cL P_L + cR P_R) Fin of an (F, Fin) pair
+    closing several diagrams with the same couplings: each diagram is then
+    i (bil . V)."""
+
+    def __init__(self, idx, fout, fin, couplings):
+        self.idx = idx
+        self.fout = fout
+        self.fin = fin
+        self.couplings = couplings
+        self.op = ('bil', fout, fin)
+
+
+def _deps(n):
+    return [c for c in n.op[1:] if hasattr(c, 'idx')]
+
+
+def schedule(pd):
+    """Order the amplitude terms greedily so that each step needs as few new
+    wavefunctions as possible (keeps live ranges short).  Returns the list
+    of (diagram index, closing form) and the bilinear nodes."""
+    def gkey(d):
+        return (d.fout.idx, d.fin.idx, FFV[(d.fin.flav, d.vec.flav)])
+    groups = {}
+    for k, d in enumerate(pd.diagrams):
+        groups.setdefault(gkey(d), []).append(k)
+    bils = {}
+    nxt = 10 ** 6
+    for key, ks in groups.items():
+        if len(ks) > 1:
+            d = pd.diagrams[ks[0]]
+            bils[key] = Bil(nxt, d.fout, d.fin, key[2])
+            nxt += 1
+
+    def need(k):
+        d = pd.diagrams[k]
+        b = bils.get(gkey(d))
+        return [d.vec, b] if b is not None else [d.fout, d.vec, d.fin]
+
+    def closure(nodes, done):
+        out, stack = set(), list(nodes)
+        while stack:
+            n = stack.pop()
+            if n.idx in done or n.idx in out:
+                continue
+            out.add(n.idx)
+            stack.extend(_deps(n))
+        return out
+
+    # pending[x] = consumers of x (wavefunctions or amplitude terms) not yet emitted
+    pending = {}
+    seen = set()
+
+    def count(n):
+        if n.idx in seen:
+            return
+        seen.add(n.idx)
+        for c in _deps(n):
+            pending[c.idx] = pending.get(c.idx, 0) + 1
+            count(c)
+    for k in range(len(pd.diagrams)):
+        for n in need(k):
+            pending[n.idx] = pending.get(n.idx, 0) + 1
+            count(n)
+    nodes = {}
+
+    def reg(n):
+        nodes[n.idx] = n
+        for c in _deps(n):
+            reg(c)
+    for k in range(len(pd.diagrams)):
+        for n in need(k):
+            reg(n)
+
+    def effect(k, done):
+        new = closure(need(k), done)
+        dec = {}
+        for m in new:
+            for c in _deps(nodes[m]):
+                dec[c.idx] = dec.get(c.idx, 0) + 1
+        for n in need(k):
+            dec[n.idx] = dec.get(n.idx, 0) + 1
+        freed = sum(1 for x, d in dec.items() if pending[x] - d == 0)
+        return new, dec, freed
+
+    done = set()
+    remaining = list(range(len(pd.diagrams)))
+    order = []
+    while remaining:
+        best, best_key = None, None
+        for k in remaining:
+            new, dec, freed = effect(k, done)
+            key = (len(new) - freed, len(new), k)
+            if best_key is None or key < best_key:
+                best, best_key = k, key
+        new, dec, freed = effect(best, done)
+        for x, d in dec.items():
+            pending[x] -= d
+        remaining.remove(best)
+        order.append(best)
+        done |= new
+    return order, bils, need
+
+
+def _node_flops(n):
+    if isinstance(n, Bil):
+        return FLOPS['ffv_bil']
+    op = n.op[0]
+    if op == 'ext':
+        return FLOPS[n.op[2]]
+    if op == 'ffv_v':
+        return FLOPS['ffv_cur_v0'] if BOSON_MASS[n.op[3]] is None else FLOPS['ffv_cur_vm']
+    return FLOPS[{'vvv': 'vvv_cur', 'vvvv': 'vvvv_cur', 'ffv_fout': 'ffv_cur_fout',
+                  'ffv_fin': 'ffv_cur_fin'}[op]]
+
+
+def schedule_cost(order, need, budget):
+    """Executed flops of the wavefunctions (with recomputation) for a
+    diagram order under a live-wavefunction budget: the same policy as
+    emit_body (compute on first use, evict the farthest next use)."""
+    import bisect
+    uses_at = {}
+    clos = []
+    for pos, k in enumerate(order):
+        out, stack = {}, list(need(k))
+        while stack:
+            n = stack.pop()
+            if n.idx in out:
+                continue
+            out[n.idx] = n
+            stack.extend(_deps(n))
+        clos.append(out)
+        for x in out:
+            uses_at.setdefault(x, []).append(pos)
+    INF = 10 ** 9
+
+    def next_use(x, pos):
+        lst = uses_at[x]
+        i = bisect.bisect_left(lst, pos)
+        return lst[i] if i < len(lst) else INF
+
+    live = {}
+    cost = 0
+
+    def ensure(n, pos, pinned):
+        nonlocal cost
+        if n.idx in live:
+            return
+        deps = _deps(n)
+        pin = pinned | {n.idx} | {d.idx for d in deps}
+        for d in deps:
+            ensure(d, pos, pin)
+        while len(live) >= budget:
+            cand = [x for x in live if x not in pin and live[x].op[0] != 'ext']
+            if not cand:
+                break
+            del live[max(cand, key=lambda x: next_use(x, pos))]
+        cost += _node_flops(n)
+        live[n.idx] = n
+
+    for pos, k in enumerate(order):
+        nd = need(k)
+        pin = {n.idx for n in nd}
+        for n in nd:
+            ensure(n, pos, pin)
+        for x in list(live):
+            if next_use(x, pos + 1) == INF and live[x].op[0] != 'ext':
+                del live[x]
+    return cost
+
+
+def optimise_order(order, need, budget, iters=4000, seed=12345):
+    """Local search (random moves of one diagram or of a block, accepted
+    when the recomputation cost does not grow) over the diagram order."""
+    import random
+    rng = random.Random(seed)
+    best = list(order)
+    best_cost = schedule_cost(best, need, budget)
+    n = len(best)
+    if n < 3:
+        return best, best_cost
+    for _ in range(iters):
+        cand = list(best)
+        i, j = sorted(rng.sample(range(n), 2))
+        r = rng.random()
+        if r < 0.4:
+            x = cand.pop(i)
+            cand.insert(j, x)
+        elif r < 0.7:
+            x = cand.pop(j)
+            cand.insert(i, x)
+        else:
+            L = rng.randint(2, min(12, n - i))
+            blk = cand[i:i + L]
+            del cand[i:i + L]
+            k = rng.randint(0, len(cand))
+            cand[k:k] = blk
+        c = schedule_cost(cand, need, budget)
+        if c <= best_cost:
+            best, best_cost = cand, c
+    return best, best_cost
 
 
 def _ksum(legs, particles):
@@ -56,9 +260,183 @@ def _coef_expr(coef, amp):
     return f"+ cx<T>{{(T){c.real!r}, (T){c.imag!r}}} * {amp}"
 
 
+def _node_code(n, name, dn, parts):
+    """C++ statement computing wavefunction n into `name`; dn = names of its
+    inputs in op order.  Returns (code, flops)."""
+    op = n.op
+    if isinstance(n, Bil):
+        cl, cr = n.couplings
+        return (f"cx<T> {name}[4]; ffv_bilinear<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, {name});",
+                FLOPS['ffv_bil'])
+    K = _ksum(n.legs, parts)
+    if op[0] == 'vvv':
+        a, b = op[1], op[2]
+        return (f"cx<T> {name}[4]; {{ const double KA[4] = {_ksum(a.legs, parts)}; "
+                f"const double KB[4] = {_ksum(b.legs, parts)}; "
+                f"vvv_cur<T>({dn[0]}, KA, {dn[1]}, KB, c.gs, {name}); }}", FLOPS['vvv_cur'])
+    if op[0] == 'vvvv':
+        s = op[1]
+        return (f"cx<T> {name}[4]; {{ const double K[4] = {K}; "
+                f"vvvv_cur<{s}, T>({dn[0]}, {dn[1]}, {dn[2]}, K, c.gs2, {name}); }}",
+                FLOPS['vvvv_cur'])
+    if op[0] == 'ffv_fout':
+        f, vec = op[1], op[2]
+        cl, cr = FFV[(f.flav, vec.flav)]
+        m, wd = FERMION_MASS[f.flav]
+        return (f"cx<T> {name}[4]; {{ const double K[4] = {K}; "
+                f"ffv_cur_fout<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{m}, c.{wd}, {name}); }}",
+                FLOPS['ffv_cur_fout'])
+    if op[0] == 'ffv_fin':
+        vec, f = op[1], op[2]
+        cl, cr = FFV[(f.flav, vec.flav)]
+        m, wd = FERMION_MASS[f.flav]
+        return (f"cx<T> {name}[4]; {{ const double K[4] = {K}; "
+                f"ffv_cur_fin<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{m}, c.{wd}, {name}); }}",
+                FLOPS['ffv_cur_fin'])
+    if op[0] == 'ffv_v':
+        fo, fi, boson = op[1], op[2], op[3]
+        cl, cr = FFV[(fo.flav, boson)]
+        bm = BOSON_MASS[boson]
+        if bm is None:
+            return (f"cx<T> {name}[4]; {{ const double K[4] = {K}; "
+                    f"ffv_cur_v0<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, {name}); }}",
+                    FLOPS['ffv_cur_v0'])
+        return (f"cx<T> {name}[4]; {{ const double K[4] = {K}; "
+                f"ffv_cur_vm<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{bm[0]}, c.{bm[1]}, {name}); }}",
+                FLOPS['ffv_cur_vm'])
+    raise ValueError(op)
+
+
+def _ext_code(n, name, npar):
+    l, routine = n.op[1], n.op[2]
+    hel = f"((hcode >> {npar - 1 - l}) & 1u) ? 1 : -1"
+    p = f"p[{l}]"
+    if routine in ('vec_in', 'vec_out'):
+        return (f"cx<T> {name}[4]; ext_vector<T>({p}, {hel}, "
+                f"{'false' if routine == 'vec_in' else 'true'}, {name});", FLOPS[routine])
+    mass = {'t': 'c.mt'}.get(n.flav, '0.0')
+    fn = {'ubar': ('ext_u', 'true'), 'u': ('ext_u', 'false'),
+          'v': ('ext_v', 'false'), 'vbar': ('ext_v', 'true')}[routine]
+    return f"cx<T> {name}[4]; {fn[0]}<T>({p}, {mass}, {hel}, {fn[1]}, {name});", FLOPS[routine]
+
+
+def emit_body(pd, coefs, order, bils, need, budget):
+    """Straight-line body of jamps() for one register budget (in live
+    wavefunctions).  Wavefunctions are computed on first use; when the
+    budget is full the live one whose next use is farthest is dropped
+    (Belady) and recomputed when needed again, its input passed through an
+    opaque copy so the compiler cannot merge the two computations back into
+    one long-lived value.  Returns (lines, algorithmic flops, executed
+    flops, peak live, recomputations)."""
+    import bisect
+    parts = pd.particles
+    npar = pd.npar
+
+    def full_closure(nodes):
+        out, stack = {}, list(nodes)
+        while stack:
+            n = stack.pop()
+            if n.idx in out:
+                continue
+            out[n.idx] = n
+            stack.extend(_deps(n))
+        return out
+
+    uses_at = {}
+    for pos, k in enumerate(order):
+        for x in full_closure(need(k)):
+            uses_at.setdefault(x, []).append(pos)
+    INF = 10 ** 9
+
+    def next_use(x, pos):
+        lst = uses_at.get(x, [])
+        i = bisect.bisect_left(lst, pos)
+        return lst[i] if i < len(lst) else INF
+
+    live = {}
+    version = {}
+    L = []
+    algo, execd = 0, 0
+    peak, recomputes = 0, 0
+    computed_once = set()
+
+    def evict(pos, pinned):
+        while len(live) >= budget:
+            cand = [x for x in live if x not in pinned and live[x][1].op[0] != 'ext']
+            if not cand:
+                return
+            victim = max(cand, key=lambda x: next_use(x, pos))
+            del live[victim]
+
+    def ensure(n, pos, pinned):
+        nonlocal algo, execd, peak, recomputes
+        if n.idx in live:
+            return live[n.idx][0]
+        deps = _deps(n)
+        pin = set(pinned) | {n.idx} | {d.idx for d in deps}
+        dn = [ensure(d, pos, pin) for d in deps]
+        evict(pos, pin)
+        v = version.get(n.idx, 0)
+        version[n.idx] = v + 1
+        base = f"b{n.idx - 10 ** 6}" if isinstance(n, Bil) else f"w{n.idx}"
+        name = base if v == 0 else f"{base}_{v}"
+        if n.op[0] == 'ext':
+            code, fl = _ext_code(n, name, npar)
+        else:
+            if v > 0:  # opaque copy of one input defeats common-subexpression merging
+                L.append(f"  cx<T> o{n.idx}_{v}[4] = {{{dn[0]}[0], {dn[0]}[1], {dn[0]}[2], {dn[0]}[3]}}; "
+                         f"opaque4(o{n.idx}_{v});")
+                dn = [f"o{n.idx}_{v}"] + dn[1:]
+                recomputes += 1
+            code, fl = _node_code(n, name, dn, parts)
+        L.append("  " + code)
+        execd += fl
+        if n.idx not in computed_once:
+            computed_once.add(n.idx)
+            algo += fl
+        live[n.idx] = (name, n)
+        peak = max(peak, len(live))
+        return name
+
+    for pos, k in enumerate(order):
+        d, cf = pd.diagrams[k], coefs[k]
+        nd = need(k)
+        pin = {n.idx for n in nd}
+        if pos % FENCE_EVERY == 0:
+            L.append("  fence(p);")
+        names = [ensure(n, pos, pin) for n in nd]
+        cl, cr = FFV[(d.fin.flav, d.vec.flav)]
+        if len(nd) == 2:   # shared bilinear . vector
+            L.append(f"  {{ const cx<T> a = times_i(mdot({names[0]}, {names[1]}));")
+            fl = FLOPS['amp_dot']
+        else:
+            L.append(f"  {{ const cx<T> a = ffv_amp<T>({names[0]}, {names[1]}, {names[2]}, "
+                     f"c.{cl}, c.{cr});")
+            fl = FLOPS['ffv_amp']
+        algo += fl
+        execd += fl
+        for kk, coef in sorted(cf.items()):
+            L.append(f"    J[{kk}] = J[{kk}] {_coef_expr(coef, 'a')};")
+            algo += FLOPS['jamp_acc']
+            execd += FLOPS['jamp_acc']
+        L.append("  }")
+        for x in list(live):
+            if next_use(x, pos + 1) == INF and live[x][1].op[0] != 'ext':
+                del live[x]
+    return L, algo, execd, peak, recomputes
+
+
+# register budget in live wavefunctions (4 complex each) per precision:
+# FP64 wavefunctions take 16 VGPRs, FP32 ones 8; the colour-flow amplitudes
+# and the momenta stay live besides them.
+BUDGET = {'f64': 12, 'f32': 36}
+OPT_ITERS = 2500
+# amplitude terms between two scheduling fences (see fence() in helas.h)
+FENCE_EVERY = 4
+
+
 def generate(name):
     pd = ProcessDiagrams(name)
-    parts = pd.particles
     npar = pd.npar
     basis = pd.colour_basis() if pd.gluons else [()]
     ncol = len(basis)
@@ -67,11 +445,12 @@ def generate(name):
     else:
         cnum, cden = [[1]], 1
     coefs = pd.jamp_coefficients()
-    flops = 0
+    order0, bils, need = schedule(pd)
     L = []
     w = L.append
     w(f"// Generated for {name}: do not edit.  {pd.ndiagrams} diagrams, "
-      f"{len(pd.diagrams)} amplitude calls, {len(pd.used) - npar} currents.")
+      f"{len(pd.diagrams)} amplitude terms, {len(pd.used) - npar} currents, "
+      f"{len(bils)} shared bilinears.")
     w(f"namespace gen_{name} {{")
     w(f"constexpr int NPAR = {npar};")
     w(f"constexpr int NCOL = {ncol};")
@@ -84,94 +463,27 @@ def generate(name):
         w("  {" + ", ".join(str(x) for x in row) + "},")
     w("};")
     w("")
+    stats = {}
+    for prec, T in (('f64', 'double'), ('f32', 'float')):
+        budget = int(os.environ.get(f'MG_BUDGET_{prec.upper()}', BUDGET[prec]))
+        order = order0
+        if schedule_cost(order0, need, budget) > schedule_cost(order0, need, 10 ** 6):
+            order, _ = optimise_order(order0, need, budget, iters=OPT_ITERS)
+        body, algo, execd, peak, rec = emit_body(pd, coefs, order, bils, need, budget)
+        stats[prec] = dict(flops_amp_per_hel=algo, flops_executed_per_hel=execd,
+                           peak_live_wavefunctions=peak, recomputed=rec)
+        w(f"__device__ __forceinline__ void jamps_{prec}(double (&p)[{npar}][4], unsigned hcode,")
+        w(f"                                          const Couplings<{T}>& c, cx<{T}> (&J)[{ncol}]) {{")
+        w(f"  using T = {T};")
+        for k in range(ncol):
+            w(f"  J[{k}] = cx<T>{{(T)0, (T)0}};")
+        L.extend(body)
+        w("}")
+        w("")
     w("template <typename T>")
-    w(f"__device__ __forceinline__ void jamps(const double (&p)[{npar}][4], unsigned hcode,")
+    w(f"__device__ __forceinline__ void jamps(double (&p)[{npar}][4], unsigned hcode,")
     w(f"                                      const Couplings<T>& c, cx<T> (&J)[{ncol}]) {{")
-    for k in range(ncol):
-        w(f"  J[{k}] = cx<T>{{(T)0, (T)0}};")
-    names = {}
-    emitted = set()
-
-    def hel(l):
-        return f"((hcode >> {npar - 1 - l}) & 1u) ? 1 : -1"
-
-    def emit_node(n):
-        nonlocal flops
-        if n.idx in emitted:
-            return
-        op = n.op
-        for ch in op[1:]:
-            if hasattr(ch, 'idx'):
-                emit_node(ch)
-        v = f"w{n.idx}"
-        names[n.idx] = v
-        emitted.add(n.idx)
-        if op[0] == 'ext':
-            l, routine = op[1], op[2]
-            p = f"p[{l}]"
-            if routine == 'vec_in':
-                w(f"  cx<T> {v}[4]; ext_vector<T>({p}, {hel(l)}, false, {v});")
-            elif routine == 'vec_out':
-                w(f"  cx<T> {v}[4]; ext_vector<T>({p}, {hel(l)}, true, {v});")
-            else:
-                mass = {'t': 'c.mt'}.get(n.flav, '0.0')
-                fn = {'ubar': ('ext_u', 'true'), 'u': ('ext_u', 'false'),
-                      'v': ('ext_v', 'false'), 'vbar': ('ext_v', 'true')}[routine]
-                w(f"  cx<T> {v}[4]; {fn[0]}<T>({p}, {mass}, {hel(l)}, {fn[1]}, {v});")
-            flops += FLOPS[routine]
-            return
-        K = _ksum(n.legs, parts)
-        if op[0] == 'vvv':
-            a, b = op[1], op[2]
-            w(f"  cx<T> {v}[4]; {{ const double KA[4] = {_ksum(a.legs, parts)}; "
-              f"const double KB[4] = {_ksum(b.legs, parts)}; "
-              f"vvv_cur<T>({names[a.idx]}, KA, {names[b.idx]}, KB, c.gs, {v}); }}")
-            flops += FLOPS['vvv_cur']
-        elif op[0] == 'vvvv':
-            s, x, y, z = op[1], op[2], op[3], op[4]
-            w(f"  cx<T> {v}[4]; {{ const double K[4] = {K}; "
-              f"vvvv_cur<{s}, T>({names[x.idx]}, {names[y.idx]}, {names[z.idx]}, K, c.gs2, {v}); }}")
-            flops += FLOPS['vvvv_cur']
-        elif op[0] == 'ffv_fout':
-            f, vec = op[1], op[2]
-            cl, cr = FFV[(f.flav, vec.flav)]
-            m, wd = FERMION_MASS[f.flav]
-            w(f"  cx<T> {v}[4]; {{ const double K[4] = {K}; "
-              f"ffv_cur_fout<T>({names[f.idx]}, {names[vec.idx]}, c.{cl}, c.{cr}, K, c.{m}, c.{wd}, {v}); }}")
-            flops += FLOPS['ffv_cur_fout']
-        elif op[0] == 'ffv_fin':
-            vec, f = op[1], op[2]
-            cl, cr = FFV[(f.flav, vec.flav)]
-            m, wd = FERMION_MASS[f.flav]
-            w(f"  cx<T> {v}[4]; {{ const double K[4] = {K}; "
-              f"ffv_cur_fin<T>({names[vec.idx]}, {names[f.idx]}, c.{cl}, c.{cr}, K, c.{m}, c.{wd}, {v}); }}")
-            flops += FLOPS['ffv_cur_fin']
-        elif op[0] == 'ffv_v':
-            fo, fi, boson = op[1], op[2], op[3]
-            cl, cr = FFV[(fo.flav, boson)]
-            bm = BOSON_MASS[boson]
-            if bm is None:
-                w(f"  cx<T> {v}[4]; {{ const double K[4] = {K}; "
-                  f"ffv_cur_v0<T>({names[fo.idx]}, {names[fi.idx]}, c.{cl}, c.{cr}, K, {v}); }}")
-                flops += FLOPS['ffv_cur_v0']
-            else:
-                w(f"  cx<T> {v}[4]; {{ const double K[4] = {K}; "
-                  f"ffv_cur_vm<T>({names[fo.idx]}, {names[fi.idx]}, c.{cl}, c.{cr}, K, c.{bm[0]}, c.{bm[1]}, {v}); }}")
-                flops += FLOPS['ffv_cur_vm']
-        else:
-            raise ValueError(op)
-
-    for d, cf in zip(pd.diagrams, coefs):
-        for n in (d.fout, d.vec, d.fin):
-            emit_node(n)
-        cl, cr = FFV[(d.fin.flav, d.vec.flav)]
-        w(f"  {{ const cx<T> a = ffv_amp<T>({names[d.fout.idx]}, {names[d.vec.idx]}, "
-          f"{names[d.fin.idx]}, c.{cl}, c.{cr});")
-        for k, coef in sorted(cf.items()):
-            w(f"    J[{k}] = J[{k}] {_coef_expr(coef, 'a')};")
-            flops += FLOPS['jamp_acc']
-        w("  }")
-        flops += FLOPS['ffv_amp']
+    w("  if constexpr (sizeof(T) == 8) jamps_f64(p, hcode, c, J); else jamps_f32(p, hcode, c, J);")
     w("}")
     w("")
     # colour sum: sum_i J_i^* (sum_j C_ij J_j) using the symmetry of C
@@ -196,8 +508,10 @@ def generate(name):
     cs_flops += 1
     meta = {
         'process': name, 'npar': npar, 'ncol': ncol, 'ndiag': pd.ndiagrams,
-        'namp': len(pd.diagrams), 'ncurrents': len(pd.used) - npar,
-        'flops_amp_per_hel': flops, 'flops_colour_per_hel': cs_flops,
+        'namp': len(pd.diagrams), 'ncurrents': len(pd.used) - npar, 'nbilinears': len(bils),
+        'flops_amp_per_hel': stats['f64']['flops_amp_per_hel'],
+        'flops_colour_per_hel': cs_flops,
+        'schedule': stats,
         'iden': IDEN[name], 'cden': cden,
     }
     return "\n".join(L) + "\n", meta
