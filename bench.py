@@ -90,7 +90,7 @@ def main():
     ap.add_argument('--process', default='ggttgg')
     ap.add_argument('--nevt', type=int, default=1 << 19)
     ap.add_argument('--seed', type=int, default=3)
-    ap.add_argument('--precisions', default='fp64,fp32amp')
+    ap.add_argument('--precisions', default='fp64,mixed,fp32amp')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--cpu-events-per-worker', type=int, default=96)
     ap.add_argument('--copy-calibration', action='store_true',

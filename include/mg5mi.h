@@ -65,8 +65,11 @@ typedef enum {
  *               sum in binary32 (VALU); momenta, propagator denominators,
  *               helicity sum and /IDEN in binary64
  *   MG_MIXED    as MG_FP32AMP but the colour sum runs on the matrix cores
- *               (MFMA) with FP32 accumulation */
-typedef enum { MG_FP64 = 0, MG_FP32AMP = 1, MG_MIXED = 2 } mg_prec_t;
+ *               with FP32 accumulation: for 24 colour flows (g g -> t t~ g g)
+ *               the jamps are split into three BF16 terms against the exact
+ *               BF16 colour numerators; otherwise FP32 MFMA operands
+ *   MG_MIXED_F32MFMA  as MG_MIXED with FP32 MFMA operands for every process */
+typedef enum { MG_FP64 = 0, MG_FP32AMP = 1, MG_MIXED = 2, MG_MIXED_F32MFMA = 3 } mg_prec_t;
 
 /* physics inputs; couplings are derived in mg_create (sin^2 theta_W in the
  * G_F scheme from alpha, G_F and mZ) */

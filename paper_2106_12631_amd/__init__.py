@@ -15,7 +15,7 @@ __all__ = ['MEEngine', 'MEWeight', 'PROCESSES', 'PRECISIONS', 'lib', 'library_pa
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 PROCESSES = {'eemumu': 0, 'ggtt': 1, 'ggttg': 2, 'ggttgg': 3}
-PRECISIONS = {'fp64': 0, 'fp32amp': 1, 'mixed': 2}
+PRECISIONS = {'fp64': 0, 'fp32amp': 1, 'mixed': 2, 'mixed_f32mfma': 3}
 
 
 class Params(ctypes.Structure):

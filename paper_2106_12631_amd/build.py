@@ -52,7 +52,8 @@ def build(force=True, verbose=True, extra_flags=(), output=None):
             failed.append(src)
             print(f"[build] {src} FAILED\n" + "\n".join(lines[-60:]), file=sys.stderr)
         elif verbose and lines:
-            print(f"[build] {src}:\n" + "\n".join(lines[-20:]), file=sys.stderr)
+            keep = lines if extra_flags else lines[-20:]
+            print(f"[build] {src}:\n" + "\n".join(keep), file=sys.stderr)
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
     lib = output or LIB

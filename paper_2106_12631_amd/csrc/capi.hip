@@ -19,6 +19,25 @@ MG_DECL(ggtt)
 MG_DECL(ggttg)
 MG_DECL(ggttgg)
 #undef MG_DECL
+#define MG_DECL(p)                                                                              \
+  int launch_sigmakin_##p##_mfma_f32(const MeArgs&, const double*, int64_t, double*, const double*, \
+                                     double*, hipStream_t);                                     \
+  int launch_sigmakin_##p##_mfma_bf16(const MeArgs&, const double*, int64_t, double*,              \
+                                      const double*, double*, hipStream_t);
+MG_DECL(eemumu)
+MG_DECL(ggtt)
+MG_DECL(ggttg)
+MG_DECL(ggttgg)
+#undef MG_DECL
+
+typedef int (*skm_fn)(const MeArgs&, const double*, int64_t, double*, const double*, double*,
+                      hipStream_t);
+static const skm_fn SKM[4][2] = {
+    {launch_sigmakin_eemumu_mfma_f32, launch_sigmakin_eemumu_mfma_bf16},
+    {launch_sigmakin_ggtt_mfma_f32, launch_sigmakin_ggtt_mfma_bf16},
+    {launch_sigmakin_ggttg_mfma_f32, launch_sigmakin_ggttg_mfma_bf16},
+    {launch_sigmakin_ggttgg_mfma_f32, launch_sigmakin_ggttgg_mfma_bf16},
+};
 
 typedef int (*sk_fn)(const MeArgs&, const double*, int64_t, double*, const double*, double*,
                      double*, hipStream_t);
@@ -29,10 +48,14 @@ static const sk_fn SK[4][2] = {
     {launch_sigmakin_ggttgg_f64, launch_sigmakin_ggttgg_f32},
 };
 
+// prec: 0 FP64, 1 FP32 amplitudes + VALU colour sum, 2 mixed (BF16-split MFMA
+// colour sum for 24 colour flows, FP32 MFMA otherwise), 3 mixed with FP32 MFMA
 int launch_sigmakin(int proc, int prec, const MeArgs& a, const double* mom, int64_t nevt,
                     double* me, const double* wgt, double* evtw, hipStream_t s) {
-  if (proc < 0 || proc > 3 || prec < 0 || prec > 1) return -1;
-  return SK[proc][prec](a, mom, nevt, me, wgt, evtw, nullptr, s);
+  if (proc < 0 || proc > 3 || prec < 0 || prec > 3) return -1;
+  if (prec <= 1) return SK[proc][prec](a, mom, nevt, me, wgt, evtw, nullptr, s);
+  const int bf16 = (prec == 2 && proc == MG_GGTTGG) ? 1 : 0;
+  return SKM[proc][bf16](a, mom, nevt, me, wgt, evtw, s);
 }
 
 int launch_sigmakin_hel(int proc, int prec, const MeArgs& a, const double* mom, int64_t nevt,
@@ -194,9 +217,8 @@ static int filter_helicities(mg_handle* h) {
 extern "C" {
 
 int mg_create(int proc, int prec, const mg_params_t* prm, mg_handle_t** out) {
-  if (!out || proc < 0 || proc > 3 || prec < 0 || prec > 2) return MG_EINVAL;
+  if (!out || proc < 0 || proc > 3 || prec < 0 || prec > 3) return MG_EINVAL;
   *out = nullptr;
-  if (prec == MG_MIXED) return MG_ENOTSUP;
   mg_params_t p = {1500.0, 132.5, 1.16639e-5, 91.188, 2.441, 173.0, 1.49, 0.118};
   if (prm) p = *prm;
   if (!(p.sqrts > 0) || !(p.alpha_inv > 0) || !(p.gfermi > 0) || !(p.mZ > 0) || p.wZ < 0 ||

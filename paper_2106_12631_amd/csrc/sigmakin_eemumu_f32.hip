@@ -8,6 +8,8 @@ namespace mg {
 struct P_eemumu {
   static constexpr int NPAR = gen_eemumu::NPAR;
   static constexpr int NCOL = gen_eemumu::NCOL;
+  static constexpr int CDEN = gen_eemumu::CDEN;
+  __device__ static __forceinline__ const int* cnum() { return &gen_eemumu::CNUM[0][0]; }
   template <typename T>
   __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<T>& c, cx<T> (&J)[NCOL]) {

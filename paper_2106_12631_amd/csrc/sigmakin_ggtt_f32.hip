@@ -8,6 +8,8 @@ namespace mg {
 struct P_ggtt {
   static constexpr int NPAR = gen_ggtt::NPAR;
   static constexpr int NCOL = gen_ggtt::NCOL;
+  static constexpr int CDEN = gen_ggtt::CDEN;
+  __device__ static __forceinline__ const int* cnum() { return &gen_ggtt::CNUM[0][0]; }
   template <typename T>
   __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<T>& c, cx<T> (&J)[NCOL]) {

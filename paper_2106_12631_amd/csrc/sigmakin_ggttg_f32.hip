@@ -8,6 +8,8 @@ namespace mg {
 struct P_ggttg {
   static constexpr int NPAR = gen_ggttg::NPAR;
   static constexpr int NCOL = gen_ggttg::NCOL;
+  static constexpr int CDEN = gen_ggttg::CDEN;
+  __device__ static __forceinline__ const int* cnum() { return &gen_ggttg::CNUM[0][0]; }
   template <typename T>
   __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<T>& c, cx<T> (&J)[NCOL]) {

@@ -8,6 +8,8 @@ namespace mg {
 struct P_ggttgg {
   static constexpr int NPAR = gen_ggttgg::NPAR;
   static constexpr int NCOL = gen_ggttgg::NCOL;
+  static constexpr int CDEN = gen_ggttgg::CDEN;
+  __device__ static __forceinline__ const int* cnum() { return &gen_ggttgg::CNUM[0][0]; }
   template <typename T>
   __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<T>& c, cx<T> (&J)[NCOL]) {

@@ -3,6 +3,7 @@
 // generated straight-line code builds the colour-flow amplitudes and the
 // colour sum gives the helicity's |M|^2, accumulated in FP64.
 #pragma once
+#include "colour_mfma.h"
 #include "common.h"
 #include "internal.h"
 
@@ -47,6 +48,49 @@ __global__ void __launch_bounds__(BS)
   const double m = acc * inv_iden;
   if (me) me[i] = m;
   if (evtw) evtw[i] = m * wgt[i];
+}
+
+// Mixed precision: FP32 amplitudes, colour sum on the matrix cores (CS =
+// ColourMfmaF32 or ColourMfmaBf16), FP64 helicity sum.  One wave per block;
+// lanes past nevt compute a copy of the last event and store nothing, so
+// every lane takes part in the wave-wide MFMA exchange.
+template <class P, template <int> class CS>
+__global__ void __launch_bounds__(64)
+    sigmakin_mixed_kernel(const double* __restrict__ mom, int64_t nevt, double* __restrict__ me,
+                          const double* __restrict__ wgt, double* __restrict__ evtw, HelList hl,
+                          Couplings<float> c, double inv_iden) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[CS<P::NCOL>::LDS_BYTES];
+  const int lane = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const bool valid = i < nevt;
+  const int64_t il = valid ? i : nevt - 1;
+  CS<P::NCOL> cs;
+  cs.init(P::cnum(), lane);
+  const double scale = inv_iden / P::CDEN;
+  double acc = 0.0;
+#pragma nounroll
+  for (int k = 0; k < hl.n; ++k) {
+    int64_t iq = il;
+    asm volatile("" : "+v"(iq));
+    double q[P::NPAR][4];
+    load_event<P>(mom, iq, q);
+    cx<float> J[P::NCOL];
+    P::template jamps<float>(q, hl.code[k], c, J);
+    acc += (double)cs.sum(lds, J, lane);
+  }
+  if (valid) {
+    const double m = acc * scale;
+    if (me) me[i] = m;
+    if (evtw) evtw[i] = m * wgt[i];
+  }
+}
+
+template <class P, template <int> class CS>
+int sigmakin_mixed_launch(const MeArgs& a, const double* mom, int64_t nevt, double* me,
+                          const double* wgt, double* evtw, hipStream_t s) {
+  const unsigned g = (unsigned)((nevt + 63) / 64);
+  sigmakin_mixed_kernel<P, CS><<<g, 64, 0, s>>>(mom, nevt, me, wgt, evtw, a.hel, a.c32, a.inv_iden);
+  return 0;
 }
 
 template <class P, typename T, int BS>

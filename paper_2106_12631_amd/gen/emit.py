@@ -428,8 +428,10 @@ def emit_body(pd, coefs, order, bils, need, budget):
 
 # register budget in live wavefunctions (4 complex each) per precision:
 # FP64 wavefunctions take 16 VGPRs, FP32 ones 8; the colour-flow amplitudes
-# and the momenta stay live besides them.
-BUDGET = {'f64': 12, 'f32': 36}
+# and the momenta stay live besides them.  'f32m' is the FP32 body used by
+# the kernel whose colour sum runs on the matrix cores (its operands need
+# registers too).
+BUDGET = {'f64': 12, 'f32': 36, 'f32m': 28}
 OPT_ITERS = 2500
 # amplitude terms between two scheduling fences (see fence() in helas.h)
 FENCE_EVERY = 4
@@ -464,7 +466,7 @@ def generate(name):
     w("};")
     w("")
     stats = {}
-    for prec, T in (('f64', 'double'), ('f32', 'float')):
+    for prec, T in (('f64', 'double'), ('f32', 'float'), ('f32m', 'float')):
         budget = int(os.environ.get(f'MG_BUDGET_{prec.upper()}', BUDGET[prec]))
         order = order0
         if schedule_cost(order0, need, budget) > schedule_cost(order0, need, 10 ** 6):

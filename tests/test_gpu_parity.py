@@ -163,6 +163,28 @@ def test_sigmakin_fp32amp_accuracy(mg, proc):
     assert float(err.max()) < 1e-3
 
 
+@pytest.mark.parametrize('proc,prec', [('ggttg', 'mixed'), ('ggttgg', 'mixed'),
+                                       ('ggttg', 'mixed_f32mfma'), ('ggttgg', 'mixed_f32mfma'),
+                                       ('ggtt', 'mixed'), ('eemumu', 'mixed')])
+def test_sigmakin_mixed_accuracy(mg, proc, prec):
+    """Matrix-core colour sum: within the mixed-precision target of the FP64
+    oracle, and close to the FP32-amplitude path (same jamps, VALU colour
+    sum); includes a ragged last wave."""
+    e = engine(mg, proc, prec)
+    n = SMALL[proc]
+    r, p_orc, w_orc = orc.sample(proc, CONFIG[proc][0], 0, n)
+    want = orc.matrix_element(proc, p_orc)
+    say('sigmakin', prec, proc, n)
+    mom = e.events_mom(p_orc)
+    got = e.sigmakin(mom, n).cpu()
+    err = rel(got, want)
+    say(proc, prec, 'max rel', float(err.max()), 'median', float(err.median()))
+    assert e.count_nonfinite(got.to(e.device)) == 0
+    assert float(err.max()) <= 1e-5
+    ref32 = engine(mg, proc, 'fp32amp').sigmakin(mom, n).cpu()
+    assert float(rel(got, ref32).max()) <= 2e-6
+
+
 @pytest.mark.parametrize('proc', list(CONFIG))
 def test_full_size_sampled(mg, proc):
     """Full benchmark size, launched as the benchmark launches it; sampled
@@ -210,7 +232,7 @@ def test_edge_cases_and_errors(mg):
     assert L.mg_sigmakin(h, mis, 1, ctypes.c_void_p(buf.data_ptr()), None, None, None) == -5
     out = ctypes.c_void_p()
     assert L.mg_create(7, 0, None, ctypes.byref(out)) == -1
-    assert L.mg_create(1, 2, None, ctypes.byref(out)) == -2
+    assert L.mg_create(1, 9, None, ctypes.byref(out)) == -1
     bad = mg.Params(**dict(mg.DEFAULT_PARAMS, sqrts=300.0))
     assert L.mg_create(1, 0, ctypes.byref(bad), ctypes.byref(out)) == -3
     # non-finite counting
