@@ -155,5 +155,8 @@ def event_weight_and_grad(proc, r, prm=DEFAULT):
     me = matrix_element(proc, p, prm, chunk=max(1, r.shape[0]))
     f = me * w
     (gf,) = torch.autograd.grad(f.sum(), r, retain_graph=True)
-    (gw,) = torch.autograd.grad(torch.log(w).sum(), r)
+    if w.requires_grad:
+        (gw,) = torch.autograd.grad(torch.log(w).sum(), r)
+    else:  # massless RAMBO: the weight depends on n and sqrt(s) only
+        gw = torch.zeros_like(r)
     return f.detach(), gf, gw
