@@ -82,6 +82,22 @@ def run_gpu(mg, torch, proc, prec, seed, nevt, steps, warmup):
     return eng, wall, k_ms, nonfinite
 
 
+def run_gradient(mg, torch, prec, nevt, steps, warmup, seed=4):
+    """Gradient workload: d(w |M|^2)/dr and d log w/dr for g g -> t t~ g."""
+    eng = mg.MEEngine('ggttg', prec)
+    rnd = eng.rng(seed, nevt)
+    for _ in range(warmup):
+        eng.adjoint(rnd, nevt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        grad, glogw, f = eng.adjoint(rnd, nevt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"events_per_s": nevt * steps / wall, "ms_per_launch": wall / steps * 1e3,
+            "nonfinite": eng.count_nonfinite(grad)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -93,6 +109,8 @@ def main():
     ap.add_argument('--precisions', default='fp64,mixed,fp32amp')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--cpu-events-per-worker', type=int, default=96)
+    ap.add_argument('--no-gradient', action='store_true',
+                    help='skip the gradient workload (g g -> t t~ g, 2^18 events)')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a plain 1 GiB device-to-device copy (HBM counter calibration)')
     args = ap.parse_args()
@@ -139,6 +157,12 @@ def main():
                          "frac": achieved / PEAK_FP64_VALU, "traffic": None,
                          "flops_per_event": flops_evt},
         }
+    gradient = None
+    if not args.no_gradient:
+        gradient = {"workload": "ggttg 262144 events seed 4: d(w |M|^2)/dr, d log w/dr "
+                                "(12 uniforms per event)"}
+        for prec in ('fp64', 'fp32amp'):
+            gradient[prec] = run_gradient(mg, torch, prec, 1 << 18, max(1, args.steps // 2), 1)
     head = results.get('fp64') or next(iter(results.values()))
     line = {
         "metric": METRIC,
@@ -160,6 +184,7 @@ def main():
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
         "variants": results,
+        "gradient": gradient,
     }
     print(json.dumps(line), flush=True)
 

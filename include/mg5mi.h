@@ -140,6 +140,21 @@ int mg_sigmakin(const mg_handle_t* h, const double* mom, int64_t nevt, double* m
 int mg_sigmakin_hel(const mg_handle_t* h, const double* mom, int64_t nevt, double* mehel,
                     void* stream);
 
+/* Gradient of the differentiable event weight f(r) = w(r) |M|^2(p(r)) of
+ * RAMBO + SIGMAKIN with respect to the nrnd uniforms of each event (the
+ * derivative of the workflow's sampling weight times matrix element,
+ * Sec. IV.a), for gradient-based phase-space adaptation:
+ *   grad_rnd[j]  = gbar[i] * df/dr_j       (AoSoA like rnd; gbar NULL = 1)
+ *   grad_logw[j] = d log w / dr_j          (optional, AoSoA like rnd)
+ *   f[i]         = w |M|^2                 (optional)
+ * Computed by forward-mode differentiation (one dual-number pass per
+ * uniform) through RAMBO, the Newton rescaling (implicit-function theorem)
+ * and the helicity amplitudes; FP64 for MG_FP64, FP32 amplitudes with FP64
+ * RAMBO and sums otherwise.  Built for e+e- -> mu+mu-, g g -> t t~ and
+ * g g -> t t~ g; MG_ENOTSUP for g g -> t t~ g g. */
+int mg_adjoint(const mg_handle_t* h, const double* rnd, int64_t nevt, const double* gbar_or_null,
+               double* grad_rnd, double* grad_logw_or_null, double* f_or_null, void* stream);
+
 /* Number of non-finite entries of x[0..n) accumulated into *d_count (a
  * device int64 the caller zeroes first). */
 int mg_count_nonfinite(const double* x, int64_t n, int64_t* d_count, void* stream);

@@ -62,6 +62,7 @@ def lib():
         'mg_sigmakin': [vp, vp, i64, vp, vp, vp, vp],
         'mg_sigmakin_hel': [vp, vp, i64, vp, vp],
         'mg_count_nonfinite': [vp, i64, vp, vp],
+        'mg_adjoint': [vp, vp, i64, vp, vp, vp, vp, vp],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -198,6 +199,21 @@ class MEEngine:
                'mg_sigmakin_hel')
         return out
 
+    def adjoint(self, rnd, nevt, gbar=None, want_logw=True, want_f=True):
+        """Gradient of f = w |M|^2 with respect to the uniforms (AoSoA like
+        rnd), optionally scaled per event by gbar; also d log w / dr and f."""
+        grad = torch.empty_like(rnd)
+        glogw = torch.empty_like(rnd) if want_logw else None
+        f = torch.empty(nevt, dtype=torch.float64, device=self.device) if want_f else None
+        _check(lib().mg_adjoint(self._h, _ptr(rnd), nevt, _ptr(gbar), _ptr(grad), _ptr(glogw),
+                                _ptr(f), _stream(self.device)), 'mg_adjoint')
+        return grad, glogw, f
+
+    def event_weight(self, r):
+        """Differentiable f(r) = w(r) |M|^2(p(r)) for event-major uniforms
+        r of shape (nevt, nrnd) (see MEWeight)."""
+        return MEWeight.apply(r, self)
+
     def count_nonfinite(self, x):
         cnt = torch.zeros(1, dtype=torch.int64, device=self.device)
         _check(lib().mg_count_nonfinite(_ptr(x), x.numel(), _ptr(cnt), _stream(self.device)),
@@ -206,8 +222,29 @@ class MEEngine:
 
 
 class MEWeight(torch.autograd.Function):
-    """Placeholder name for the differentiable event weight (adjoint kernel)."""
+    """f(r) = w(r) |M|^2(p(r)) per event as a differentiable torch function.
+
+    forward: RAMBO and SIGMAKIN kernels (mg_rambo, mg_sigmakin);
+    backward: the gradient kernel (mg_adjoint) with gbar = grad_output,
+    so r.grad[i, j] = grad_output[i] * df_i/dr_ij.
+    r: float64 device tensor (nevt, nrnd) of uniforms in (0, 1).
+    """
 
     @staticmethod
-    def forward(ctx, *args):
-        raise NotImplementedError("the adjoint kernel is not built yet")
+    def forward(ctx, r, engine):
+        nevt = r.shape[0]
+        rnd = engine.events_rnd(r.detach())
+        mom, wgt = engine.rambo(rnd, nevt)
+        _, evtw = engine.sigmakin(mom, nevt, wgt=wgt)
+        ctx.engine = engine
+        ctx.save_for_backward(r.detach())
+        return evtw
+
+    @staticmethod
+    def backward(ctx, gout):
+        (r,) = ctx.saved_tensors
+        eng = ctx.engine
+        nevt = r.shape[0]
+        grad, _, _ = eng.adjoint(eng.events_rnd(r), nevt, gbar=gout.contiguous().to(torch.float64),
+                                 want_logw=False, want_f=False)
+        return eng.rnd_events(grad, nevt), None

@@ -64,6 +64,13 @@ int launch_sigmakin_hel(int proc, int prec, const MeArgs& a, const double* mom, 
   return SK[proc][prec](a, mom, nevt, nullptr, nullptr, nullptr, mehel, s);
 }
 
+int launch_grad_eemumu(int, const MeArgs&, const RamboArgs&, const double*, int64_t, const double*,
+                       double*, double*, double*, hipStream_t);
+int launch_grad_ggtt(int, const MeArgs&, const RamboArgs&, const double*, int64_t, const double*,
+                     double*, double*, double*, hipStream_t);
+int launch_grad_ggttg(int, const MeArgs&, const RamboArgs&, const double*, int64_t, const double*,
+                      double*, double*, double*, hipStream_t);
+
 __global__ void __launch_bounds__(256) count_nonfinite_kernel(const double* __restrict__ x,
                                                               int64_t n,
                                                               unsigned long long* count) {
@@ -313,6 +320,35 @@ int mg_sigmakin_hel(const mg_handle_t* h, const double* mom, int64_t nevt, doubl
   const int prec = h->prec == MG_FP64 ? 0 : 1;
   if (launch_sigmakin_hel(h->proc, prec, h->me, mom, nevt, mehel, (hipStream_t)stream))
     return MG_ENOTSUP;
+  return hip_status();
+}
+
+int mg_adjoint(const mg_handle_t* h, const double* rnd, int64_t nevt, const double* gbar_or_null,
+               double* grad_rnd, double* grad_logw_or_null, double* f_or_null, void* stream) {
+  if (!h || nevt < 0 || (nevt > 0 && (!rnd || !grad_rnd))) return MG_EINVAL;
+  if (!aligned8(rnd) || !aligned8(gbar_or_null) || !aligned8(grad_rnd) ||
+      !aligned8(grad_logw_or_null) || !aligned8(f_or_null))
+    return MG_EALIGN;
+  if (h->proc == MG_GGTTGG) return MG_ENOTSUP;
+  if (nevt == 0) return MG_OK;
+  const int prec = h->prec == MG_FP64 ? 0 : 1;
+  hipStream_t s = (hipStream_t)stream;
+  int rc = 0;
+  switch (h->proc) {
+    case MG_EEMUMU:
+      rc = launch_grad_eemumu(prec, h->me, h->rambo, rnd, nevt, gbar_or_null, grad_rnd,
+                              grad_logw_or_null, f_or_null, s);
+      break;
+    case MG_GGTT:
+      rc = launch_grad_ggtt(prec, h->me, h->rambo, rnd, nevt, gbar_or_null, grad_rnd,
+                            grad_logw_or_null, f_or_null, s);
+      break;
+    case MG_GGTTG:
+      rc = launch_grad_ggttg(prec, h->me, h->rambo, rnd, nevt, gbar_or_null, grad_rnd,
+                             grad_logw_or_null, f_or_null, s);
+      break;
+  }
+  if (rc) return MG_ENOTSUP;
   return hip_status();
 }
 

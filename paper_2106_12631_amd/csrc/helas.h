@@ -17,22 +17,119 @@
 //   propagators  vector -i g/K^2 (massless) or -i (g - K K/M^2)/(K^2 - M^2 + i M W),
 //                fermion i (P-slash + m)/(P^2 - m^2 + i m w)
 //
-// Momenta are always FP64 (kin = momentum flowing into the diagram); the
-// amplitude type T is double (FP64 path) or float (mixed path).  Every
-// momentum-only quantity -- square roots of the external momenta and the
-// propagator denominators -- is formed in FP64 and rounded to T afterwards.
+// Two scalar types: R for momenta (double, or dual<double> when the
+// routines are differentiated in forward mode) and T for the amplitudes
+// (double or float, or their duals).  Every momentum-only quantity -- square
+// roots of the external momenta and the propagator denominators -- is
+// formed in R and rounded to T afterwards.  Couplings are plain reals of the
+// base type of T.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace mg {
 
+// the dual-number overloads below must not hide the real ones
+using ::fabs;
+using ::log;
+using ::sincos;
+using ::sqrt;
+
+// ---------------------------------------------------------------------------
+// forward-mode dual numbers: value and one directional derivative
+// ---------------------------------------------------------------------------
+template <typename F>
+struct dual {
+  F v, d;
+  dual() = default;
+  __host__ __device__ constexpr dual(F value) : v(value), d(F(0)) {}
+  __host__ __device__ constexpr dual(F value, F deriv) : v(value), d(deriv) {}
+  template <typename G>
+  __host__ __device__ explicit constexpr dual(const dual<G>& o) : v(F(o.v)), d(F(o.d)) {}
+};
+
+template <typename F>
+__device__ __forceinline__ dual<F> operator+(dual<F> a, dual<F> b) { return {a.v + b.v, a.d + b.d}; }
+template <typename F>
+__device__ __forceinline__ dual<F> operator-(dual<F> a, dual<F> b) { return {a.v - b.v, a.d - b.d}; }
+template <typename F>
+__device__ __forceinline__ dual<F> operator-(dual<F> a) { return {-a.v, -a.d}; }
+template <typename F>
+__device__ __forceinline__ dual<F> operator*(dual<F> a, dual<F> b) {
+  return {a.v * b.v, a.v * b.d + a.d * b.v};
+}
+template <typename F>
+__device__ __forceinline__ dual<F> operator/(dual<F> a, dual<F> b) {
+  const F q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+template <typename F>
+__device__ __forceinline__ dual<F> operator+(dual<F> a, F b) { return {a.v + b, a.d}; }
+template <typename F>
+__device__ __forceinline__ dual<F> operator+(F a, dual<F> b) { return {a + b.v, b.d}; }
+template <typename F>
+__device__ __forceinline__ dual<F> operator-(dual<F> a, F b) { return {a.v - b, a.d}; }
+template <typename F>
+__device__ __forceinline__ dual<F> operator-(F a, dual<F> b) { return {a - b.v, -b.d}; }
+template <typename F>
+__device__ __forceinline__ dual<F> operator*(dual<F> a, F b) { return {a.v * b, a.d * b}; }
+template <typename F>
+__device__ __forceinline__ dual<F> operator*(F a, dual<F> b) { return {a * b.v, a * b.d}; }
+template <typename F>
+__device__ __forceinline__ dual<F> operator/(dual<F> a, F b) { return {a.v / b, a.d / b}; }
+template <typename F>
+__device__ __forceinline__ dual<F> operator/(F a, dual<F> b) {
+  const F q = a / b.v;
+  return {q, -q * b.d / b.v};
+}
+template <typename F>
+__device__ __forceinline__ dual<F>& operator+=(dual<F>& a, dual<F> b) { return a = a + b; }
+template <typename F>
+__device__ __forceinline__ dual<F>& operator-=(dual<F>& a, dual<F> b) { return a = a - b; }
+template <typename F>
+__device__ __forceinline__ dual<F>& operator*=(dual<F>& a, dual<F> b) { return a = a * b; }
+// sqrt with derivative 0 at exactly 0: only constant momenta (the incoming
+// beams along the z axis) reach it, with a zero tangent.
+template <typename F>
+__device__ __forceinline__ dual<F> sqrt(dual<F> a) {
+  const F r = sqrt(a.v);
+  return {r, r > F(0) ? a.d / (F(2) * r) : F(0)};
+}
+template <typename F>
+__device__ __forceinline__ dual<F> log(dual<F> a) { return {log(a.v), a.d / a.v}; }
+template <typename F>
+__device__ __forceinline__ dual<F> fabs(dual<F> a) { return a.v < F(0) ? -a : a; }
+template <typename F>
+__device__ __forceinline__ void sincos(dual<F> a, dual<F>* s, dual<F>* c) {
+  F sv, cv;
+  sincos(a.v, &sv, &cv);
+  *s = {sv, cv * a.d};
+  *c = {cv, -sv * a.d};
+}
+
+template <typename X>
+struct base_of {
+  using type = X;
+};
+template <typename F>
+struct base_of<dual<F>> {
+  using type = F;
+};
+template <typename X>
+using base_t = typename base_of<X>::type;
+
+__device__ __forceinline__ double val(double x) { return x; }
+__device__ __forceinline__ float val(float x) { return x; }
+template <typename F>
+__device__ __forceinline__ F val(dual<F> x) { return x.v; }
+
+// ---------------------------------------------------------------------------
+// complex numbers
+// ---------------------------------------------------------------------------
 template <typename T>
 struct cx {
   T r, i;
 };
 
-template <typename T>
-__device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
 template <typename T>
 __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
 template <typename T>
@@ -45,24 +142,36 @@ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
 }
 template <typename T>
 __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+template <typename F>
+__device__ __forceinline__ cx<dual<F>> operator*(F s, cx<dual<F>> a) { return {s * a.r, s * a.i}; }
 template <typename T>
 __device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.i, a.r}; }
 template <typename T>
 __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.r, -a.i}; }
 
-// 1 / (re + i im) formed in FP64, rounded to T
-template <typename T>
-__device__ __forceinline__ cx<T> inv_den(double re, double im) {
-  const double n = 1.0 / (re * re + im * im);
+// 1 / (re + i im) formed in R, rounded to T
+template <typename T, typename R>
+__device__ __forceinline__ cx<T> inv_den(R re, R im) {
+  const R n = 1.0 / (re * re + im * im);
   return cx<T>{(T)(re * n), (T)(-im * n)};
 }
 
 // Opaque copy: the compiler must assume the four components changed, so a
 // wavefunction recomputed from it is not merged with an earlier computation.
+__device__ __forceinline__ void opaque(double& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void opaque(float& x) { asm volatile("" : "+v"(x)); }
+template <typename F>
+__device__ __forceinline__ void opaque(dual<F>& x) {
+  opaque(x.v);
+  opaque(x.d);
+}
 template <typename T>
 __device__ __forceinline__ void opaque4(cx<T> (&w)[4]) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) asm volatile("" : "+v"(w[k].r), "+v"(w[k].i));
+  for (int k = 0; k < 4; ++k) {
+    opaque(w[k].r);
+    opaque(w[k].i);
+  }
 }
 
 // Scheduling fence between groups of amplitude terms: the momenta are made
@@ -70,12 +179,44 @@ __device__ __forceinline__ void opaque4(cx<T> (&w)[4]) {
 // of another group and kept live in between) and the machine scheduler may
 // not move instructions across the fence.  The generated code orders its
 // work to bound the number of live wavefunctions; the fence keeps that order.
-template <int N>
-__device__ __forceinline__ void fence(double (&p)[N][4]) {
+template <int N, typename R>
+__device__ __forceinline__ void fence(R (&p)[N][4]) {
 #pragma unroll
-  for (int k = 0; k < N; ++k) asm volatile("" : "+v"(p[k][0]), "+v"(p[k][1]), "+v"(p[k][2]), "+v"(p[k][3]));
+  for (int k = 0; k < N; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) opaque(p[k][m]);
   __builtin_amdgcn_sched_barrier(0);
 }
+
+// Colour-flow amplitudes: accumulated in registers (cx<T>&) or in this
+// lane's slots of an LDS array (LdsJamps, stride 64 lanes).  The LDS
+// accesses are volatile so that the compiler keeps them in LDS instead of
+// forwarding them back into registers.
+template <typename T>
+__device__ __forceinline__ void jacc(cx<T>& j, cx<T> v) { j = j + v; }
+
+template <typename T>
+struct LdsRef {
+  T* p;  // real part; imaginary part at p + 64
+  __device__ __forceinline__ cx<T> get() const {
+    volatile T* v = p;
+    return cx<T>{v[0], v[64]};
+  }
+  __device__ __forceinline__ LdsRef& operator=(cx<T> x) {
+    volatile T* v = p;
+    v[0] = x.r;
+    v[64] = x.i;
+    return *this;
+  }
+};
+template <typename T>
+__device__ __forceinline__ void jacc(LdsRef<T> j, cx<T> v) { j = j.get() + v; }
+
+template <typename T>
+struct LdsJamps {
+  T* base;  // &lds[0][0][lane]: layout [flow][re/im][64 lanes]
+  __device__ __forceinline__ LdsRef<T> operator[](int k) const { return LdsRef<T>{base + 128 * k}; }
+};
 
 // ---------------------------------------------------------------------------
 // external wavefunctions
@@ -84,74 +225,73 @@ __device__ __forceinline__ void fence(double (&p)[N][4]) {
 // Polarisation vector eps^mu(p, lam) of a massless vector boson; conj = true
 // gives eps* (outgoing).  eps = (-lam e1 - i e2)/sqrt2 with
 // e1 = (0, cth cph, cth sph, -sth), e2 = (0, -sph, cph, 0); phi = 0 when pT = 0.
-template <typename T>
-__device__ __forceinline__ void ext_vector(const double p[4], int lam, bool conjugate, cx<T> w[4]) {
-  const double kt2 = p[1] * p[1] + p[2] * p[2];
-  const double K = sqrt(kt2 + p[3] * p[3]);
-  const double kt = sqrt(kt2);
-  const double cth = p[3] / K, sth = kt / K;
-  double cph = 1.0, sph = 0.0;
-  if (kt > 0.0) {
-    cph = p[1] / kt;
-    sph = p[2] / kt;
+template <typename T, typename R>
+__device__ __forceinline__ void ext_vector(const R p[4], int lam, bool conjugate, cx<T> w[4]) {
+  const R kt2 = p[1] * p[1] + p[2] * p[2];
+  const R K = sqrt(kt2 + p[3] * p[3]);
+  const R kt = sqrt(kt2);
+  const R iK = 1.0 / K;
+  const R cth = p[3] * iK, sth = kt * iK;
+  R cph = 1.0, sph = 0.0;
+  if (val(kt) > 0.0) {
+    const R ikt = 1.0 / kt;
+    cph = p[1] * ikt;
+    sph = p[2] * ikt;
   }
   const double r2 = 0.70710678118654752440;
   const double a = -lam * r2;             // coefficient of e1 (real part)
   const double b = conjugate ? r2 : -r2;  // coefficient of e2 (imaginary part)
-  w[0] = cx<T>{(T)0, (T)0};
-  w[1] = cx<T>{(T)(a * cth * cph), (T)(b * -sph)};
+  w[0] = cx<T>{(T)0.0, (T)0.0};
+  w[1] = cx<T>{(T)(a * cth * cph), (T)(-b * sph)};
   w[2] = cx<T>{(T)(a * cth * sph), (T)(b * cph)};
-  w[3] = cx<T>{(T)(a * -sth), (T)0};
+  w[3] = cx<T>{(T)(-a * sth), (T)0.0};
 }
 
 // Two-component helicity state for the direction of p.  P + pz is formed as
 // pT^2 / (P - pz) when pz < 0 to avoid cancellation; along -z the limit
 // theta = pi, phi = 0 gives chi+ = (0, 1), chi- = (-1, 0).
-struct chi_pair {
-  double pr, pi_;  // chi component with the phase (px + i py)/nrm
-  double a;        // real component (P + pz)/nrm
-  bool mz;         // direction is -z
-};
-
-__device__ __forceinline__ void helicity_chi(const double p[4], int lam, double& c0r, double& c0i,
-                                             double& c1r, double& c1i) {
-  const double pt2 = p[1] * p[1] + p[2] * p[2];
-  const double P = sqrt(pt2 + p[3] * p[3]);
-  double ppz;
-  if (p[3] >= 0.0) {
+template <typename R>
+__device__ __forceinline__ void helicity_chi(const R p[4], int lam, R& c0r, R& c0i, R& c1r, R& c1i) {
+  const R pt2 = p[1] * p[1] + p[2] * p[2];
+  const R P = sqrt(pt2 + p[3] * p[3]);
+  R ppz;
+  if (val(p[3]) >= 0.0) {
     ppz = P + p[3];
   } else {
-    const double d = P - p[3];
-    ppz = d > 0.0 ? pt2 / d : 0.0;
+    const R d = P - p[3];
+    ppz = val(d) > 0.0 ? pt2 / d : R(0.0);
   }
-  if (!(ppz > 0.0)) {  // along -z
-    if (lam > 0) { c0r = 0; c0i = 0; c1r = 1; c1i = 0; }
-    else { c0r = -1; c0i = 0; c1r = 0; c1i = 0; }
+  if (!(val(ppz) > 0.0)) {  // along -z
+    c0i = 0.0;
+    c1i = 0.0;
+    if (lam > 0) { c0r = 0.0; c1r = 1.0; }
+    else { c0r = -1.0; c1r = 0.0; }
     return;
   }
-  const double nrm = 1.0 / sqrt(2.0 * P * ppz);
+  const R nrm = 1.0 / sqrt(2.0 * P * ppz);
   if (lam > 0) {  // (P + pz, px + i py) / nrm
-    c0r = ppz * nrm; c0i = 0;
+    c0r = ppz * nrm; c0i = 0.0;
     c1r = p[1] * nrm; c1i = p[2] * nrm;
   } else {        // (-(px - i py), P + pz) / nrm
     c0r = -p[1] * nrm; c0i = p[2] * nrm;
-    c1r = ppz * nrm; c1i = 0;
+    c1r = ppz * nrm; c1i = 0.0;
   }
 }
 
 // (sqrt(E - lam P), sqrt(E + lam P)); E - P = m^2 / (E + P), exactly 0 if m = 0
-__device__ __forceinline__ void omegas(const double p[4], double m, int lam, double& wm, double& wp) {
-  const double P = sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
-  const double epp = p[0] + P;
-  const double emp = (m == 0.0) ? 0.0 : m * m / epp;
-  const double se = sqrt(emp), sp = sqrt(epp);
+template <typename R>
+__device__ __forceinline__ void omegas(const R p[4], double m, int lam, R& wm, R& wp) {
+  const R P = sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+  const R epp = p[0] + P;
+  const R emp = (m == 0.0) ? R(0.0) : m * m / epp;
+  const R se = sqrt(emp), sp = sqrt(epp);
   if (lam > 0) { wm = se; wp = sp; } else { wm = sp; wp = se; }
 }
 
 // u(p, lam) = (sqrt(E - lam P) chi_lam, sqrt(E + lam P) chi_lam); bar = u^dagger gamma^0
-template <typename T>
-__device__ __forceinline__ void ext_u(const double p[4], double m, int lam, bool barred, cx<T> w[4]) {
-  double wm, wp, c0r, c0i, c1r, c1i;
+template <typename T, typename R>
+__device__ __forceinline__ void ext_u(const R p[4], double m, int lam, bool barred, cx<T> w[4]) {
+  R wm, wp, c0r, c0i, c1r, c1i;
   omegas(p, m, lam, wm, wp);
   helicity_chi(p, lam, c0r, c0i, c1r, c1i);
   const double s = barred ? -1.0 : 1.0;  // conjugation flips the imaginary parts
@@ -162,9 +302,9 @@ __device__ __forceinline__ void ext_u(const double p[4], double m, int lam, bool
 }
 
 // v(p, lam) = (sqrt(E + lam P) chi_-lam, -sqrt(E - lam P) chi_-lam)
-template <typename T>
-__device__ __forceinline__ void ext_v(const double p[4], double m, int lam, bool barred, cx<T> w[4]) {
-  double wm, wp, c0r, c0i, c1r, c1i;
+template <typename T, typename R>
+__device__ __forceinline__ void ext_v(const R p[4], double m, int lam, bool barred, cx<T> w[4]) {
+  R wm, wp, c0r, c0i, c1r, c1i;
   omegas(p, m, lam, wm, wp);
   helicity_chi(p, -lam, c0r, c0i, c1r, c1i);
   const double s = barred ? -1.0 : 1.0;
@@ -205,11 +345,6 @@ __device__ __forceinline__ void mrow(const blk<T>& m, cx<T> x0, cx<T> x1, cx<T>&
   y1 = x0 * m.b + x1 * m.d;
 }
 
-// real momentum blocks sK = s.K, sbK = sb.K
-struct rblk {
-  double k0p3, k0m3, k1, k2;
-};
-
 // column: (s.K) x with s.K = [[K0-K3, -(K1 - i K2)], [-(K1 + i K2), K0+K3]]
 template <typename T>
 __device__ __forceinline__ void sK_col(const T K[4], cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
@@ -239,12 +374,13 @@ __device__ __forceinline__ void sbK_row(const T K[4], cx<T> x0, cx<T> x1, cx<T>&
   y1 = x0 * m01 + (K[0] - K[3]) * x1;
 }
 
-template <typename T>
-__device__ __forceinline__ void to_T(const double K[4], T k[4]) {
+template <typename T, typename R>
+__device__ __forceinline__ void to_T(const R K[4], T k[4]) {
   k[0] = (T)K[0]; k[1] = (T)K[1]; k[2] = (T)K[2]; k[3] = (T)K[3];
 }
 
-__device__ __forceinline__ double msq(const double K[4]) {
+template <typename R>
+__device__ __forceinline__ R msq(const R K[4]) {
   return K[0] * K[0] - K[1] * K[1] - K[2] * K[2] - K[3] * K[3];
 }
 
@@ -263,8 +399,8 @@ __device__ __forceinline__ cx<T> mdot(const T k[4], const cx<T> b[4]) {
 
 // bilinear J^mu = F gamma^mu (cL P_L + cR P_R) G for row F, column G
 template <typename T>
-__device__ __forceinline__ void ffv_bilinear(const cx<T> F[4], const cx<T> G[4], T cL, T cR,
-                                             cx<T> J[4]) {
+__device__ __forceinline__ void ffv_bilinear(const cx<T> F[4], const cx<T> G[4], base_t<T> cL,
+                                             base_t<T> cR, cx<T> J[4]) {
   // a = F_L s^mu G_R, b = F_R sb^mu G_L (sb^mu = (1, -sigma))
   const cx<T> a00 = F[0] * G[2], a11 = F[1] * G[3], a01 = F[0] * G[3], a10 = F[1] * G[2];
   const cx<T> b00 = F[2] * G[0], b11 = F[3] * G[1], b01 = F[2] * G[1], b10 = F[3] * G[0];
@@ -277,8 +413,8 @@ __device__ __forceinline__ void ffv_bilinear(const cx<T> F[4], const cx<T> G[4],
 
 // amplitude i F V-slash (cL P_L + cR P_R) G
 template <typename T>
-__device__ __forceinline__ cx<T> ffv_amp(const cx<T> F[4], const cx<T> V[4], const cx<T> G[4], T cL,
-                                         T cR) {
+__device__ __forceinline__ cx<T> ffv_amp(const cx<T> F[4], const cx<T> V[4], const cx<T> G[4],
+                                         base_t<T> cL, base_t<T> cR) {
   cx<T> J[4];
   ffv_bilinear(F, G, cL, cR, J);
   return times_i(mdot(J, V));
@@ -286,9 +422,9 @@ __device__ __forceinline__ cx<T> ffv_amp(const cx<T> F[4], const cx<T> V[4], con
 
 // vector current from F, G through a massless (photon, gluon) propagator:
 // (-i/K^2) i J^mu = J^mu / K^2
-template <typename T>
-__device__ __forceinline__ void ffv_cur_v0(const cx<T> F[4], const cx<T> G[4], T cL, T cR,
-                                           const double K[4], cx<T> out[4]) {
+template <typename T, typename R>
+__device__ __forceinline__ void ffv_cur_v0(const cx<T> F[4], const cx<T> G[4], base_t<T> cL,
+                                           base_t<T> cR, const R K[4], cx<T> out[4]) {
   cx<T> J[4];
   ffv_bilinear(F, G, cL, cR, J);
   const T rk = (T)(1.0 / msq(K));
@@ -297,22 +433,24 @@ __device__ __forceinline__ void ffv_cur_v0(const cx<T> F[4], const cx<T> G[4], T
 
 // vector current through a massive propagator in unitary gauge:
 // (J - K (K.J)/M^2) / (K^2 - M^2 + i M W)
-template <typename T>
-__device__ __forceinline__ void ffv_cur_vm(const cx<T> F[4], const cx<T> G[4], T cL, T cR,
-                                           const double K[4], double M, double W, cx<T> out[4]) {
+template <typename T, typename R>
+__device__ __forceinline__ void ffv_cur_vm(const cx<T> F[4], const cx<T> G[4], base_t<T> cL,
+                                           base_t<T> cR, const R K[4], double mass, double width,
+                                           cx<T> out[4]) {
   cx<T> J[4];
   ffv_bilinear(F, G, cL, cR, J);
   T k[4];
   to_T(K, k);
-  const cx<T> kj = (T)(1.0 / (M * M)) * mdot(k, J);
-  const cx<T> d = inv_den<T>(msq(K) - M * M, M * W);
+  const cx<T> kj = (T)(1.0 / (mass * mass)) * mdot(k, J);
+  const cx<T> d = inv_den<T>(msq(K) - mass * mass, R(mass * width));
   for (int m = 0; m < 4; ++m) out[m] = d * (J[m] - k[m] * kj);
 }
 
 // flow-in fermion current: i(K-slash + m)/D * i V-slash (cL P_L + cR P_R) G
-template <typename T>
-__device__ __forceinline__ void ffv_cur_fin(const cx<T> V[4], const cx<T> G[4], T cL, T cR,
-                                            const double K[4], double m, double w, cx<T> out[4]) {
+template <typename T, typename R>
+__device__ __forceinline__ void ffv_cur_fin(const cx<T> V[4], const cx<T> G[4], base_t<T> cL,
+                                            base_t<T> cR, const R K[4], double m, double w,
+                                            cx<T> out[4]) {
   blk<T> s, sb;
   slash_blocks(V, s, sb);
   // phi = V-slash (cL G_L, cR G_R) = (sV cR G_R, sbV cL G_L)
@@ -326,7 +464,7 @@ __device__ __forceinline__ void ffv_cur_fin(const cx<T> V[4], const cx<T> G[4], 
   cx<T> y0, y1, y2, y3;
   sK_col(k, f2, f3, y0, y1);
   sbK_col(k, f0, f1, y2, y3);
-  const cx<T> d = -inv_den<T>(msq(K) - m * m, m * w);  // i * i = -1
+  const cx<T> d = -inv_den<T>(msq(K) - m * m, R(m * w));  // i * i = -1
   out[0] = d * (y0 + mm * f0);
   out[1] = d * (y1 + mm * f1);
   out[2] = d * (y2 + mm * f2);
@@ -334,9 +472,10 @@ __device__ __forceinline__ void ffv_cur_fin(const cx<T> V[4], const cx<T> G[4], 
 }
 
 // flow-out fermion current: F i V-slash (cL P_L + cR P_R) * i(-K-slash + m)/D
-template <typename T>
-__device__ __forceinline__ void ffv_cur_fout(const cx<T> F[4], const cx<T> V[4], T cL, T cR,
-                                             const double K[4], double m, double w, cx<T> out[4]) {
+template <typename T, typename R>
+__device__ __forceinline__ void ffv_cur_fout(const cx<T> F[4], const cx<T> V[4], base_t<T> cL,
+                                             base_t<T> cR, const R K[4], double m, double w,
+                                             cx<T> out[4]) {
   blk<T> s, sb;
   slash_blocks(V, s, sb);
   // row phi = F [[0, sV cR], [sbV cL, 0]] = (F_R sbV cL, F_L sV cR)
@@ -351,7 +490,7 @@ __device__ __forceinline__ void ffv_cur_fout(const cx<T> F[4], const cx<T> V[4],
   cx<T> y0, y1, y2, y3;
   sbK_row(k, f2, f3, y0, y1);
   sK_row(k, f0, f1, y2, y3);
-  const cx<T> d = -inv_den<T>(msq(K) - m * m, m * w);
+  const cx<T> d = -inv_den<T>(msq(K) - m * m, R(m * w));
   out[0] = d * (mm * f0 - y0);
   out[1] = d * (mm * f1 - y1);
   out[2] = d * (mm * f2 - y2);
@@ -364,10 +503,10 @@ __device__ __forceinline__ void ffv_cur_fout(const cx<T> F[4], const cx<T> V[4],
 
 // three-gluon current with legs (out, A, B), colour f^{out A B}:
 // (-i/K^2) g [A (-(2kA + kB).B) + (A.B)(kA - kB) + B ((kA + 2kB).A)]
-template <typename T>
-__device__ __forceinline__ void vvv_cur(const cx<T> A[4], const double KA[4], const cx<T> B[4],
-                                        const double KB[4], T g, cx<T> out[4]) {
-  double qa[4], qb[4], dk[4], K[4];
+template <typename T, typename R>
+__device__ __forceinline__ void vvv_cur(const cx<T> A[4], const R KA[4], const cx<T> B[4],
+                                        const R KB[4], base_t<T> g, cx<T> out[4]) {
+  R qa[4], qb[4], dk[4], K[4];
   for (int m = 0; m < 4; ++m) {
     qa[m] = -(2.0 * KA[m] + KB[m]);
     qb[m] = KA[m] + 2.0 * KB[m];
@@ -380,16 +519,16 @@ __device__ __forceinline__ void vvv_cur(const cx<T> A[4], const double KA[4], co
   to_T(dk, tdk);
   const cx<T> ca = mdot(tqa, B), cb = mdot(tqb, A), ab = mdot(A, B);
   // (-i g / K^2) [...]
-  const cx<T> pre{(T)0, (T)(-1.0 / msq(K)) * g};
+  const cx<T> pre{(T)0.0, (T)(-1.0 / msq(K)) * g};
   for (int m = 0; m < 4; ++m) out[m] = pre * (A[m] * ca + tdk[m] * ab + B[m] * cb);
 }
 
 // four-gluon current, structure s (1, 2, 3), legs (out, X, Y, Z):
 //   s=1: Y (X.Z) - Z (X.Y)   s=2: X (Y.Z) - Z (X.Y)   s=3: X (Y.Z) - Y (X.Z)
 // times (-i g^2)(-i/K^2) = -g^2/K^2
-template <int S, typename T>
+template <int S, typename T, typename R>
 __device__ __forceinline__ void vvvv_cur(const cx<T> X[4], const cx<T> Y[4], const cx<T> Z[4],
-                                         const double K[4], T g2, cx<T> out[4]) {
+                                         const R K[4], base_t<T> g2, cx<T> out[4]) {
   const T pre = (T)(-1.0 / msq(K)) * g2;
   if (S == 1) {
     const cx<T> xz = pre * mdot(X, Z), xy = pre * mdot(X, Y);

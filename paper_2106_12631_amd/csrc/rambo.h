@@ -1,0 +1,121 @@
+// RAMBO phase space for one event (Sec. IV.a/IV.b phase-space sampler;
+// R. Kleiss, W.J. Stirling, S.D. Ellis, Comput. Phys. Commun. 40 (1986) 359).
+//
+// Four uniforms per final-state particle give an isotropic massless q_i
+// with energy -ln(r2 r3); the q_i are boosted to the rest frame of their sum
+// and scaled to sqrt(s); masses are introduced by a Newton solve for the
+// common scale xi of the three-momenta, in FP64.  Templated on the real
+// type R: double, or dual<double> to carry the derivative with respect to
+// one uniform (forward mode).  For duals the Newton solve runs on the values
+// and xi's derivative follows from the implicit-function theorem applied to
+// sum_i sqrt(m_i^2 + xi^2 E_i^2) = sqrt(s), whose partial derivatives are
+// xi^2 E_i / k_i^0 (in E_i) and sum_i xi E_i^2 / k_i^0 (in xi):
+//   dxi = -xi (sum_i E_i dE_i / k_i^0) / (sum_i E_i^2 / k_i^0).
+#pragma once
+#include "helas.h"
+#include "internal.h"
+
+namespace mg {
+
+__device__ __forceinline__ double with_xi_derivative(double xi, const double*, const double*,
+                                                     const RamboArgs&, int) {
+  return xi;
+}
+template <typename F>
+__device__ __forceinline__ dual<F> with_xi_derivative(double xi, const dual<F>* E, const double*,
+                                                      const RamboArgs& a, int nf) {
+  F num = 0, den = 0;
+  for (int i = 0; i < nf; ++i) {
+    const double Ev = E[i].v;
+    const double k0 = sqrt(a.m2[i] + xi * xi * Ev * Ev);
+    num += Ev * E[i].d / k0;
+    den += Ev * Ev / k0;
+  }
+  return dual<F>(xi, -xi * num / den);
+}
+
+// p[0], p[1] are the incoming momenta along +z and -z; returns false (and a
+// NaN weight) if the Newton solve did not converge.
+template <int NF, typename R>
+__device__ __forceinline__ bool rambo(const R (&r)[4 * NF], const RamboArgs& a,
+                                      R (&p)[NF + 2][4], R& w) {
+  const double twopi = 6.283185307179586476925286766559;
+  R q[NF][4];
+  R Q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    const R c = 2.0 * r[4 * i] - 1.0;
+    const R st = sqrt(1.0 - c * c);
+    R sph, cph;
+    sincos(twopi * r[4 * i + 1], &sph, &cph);
+    const R q0 = -log(r[4 * i + 2] * r[4 * i + 3]);
+    q[i][0] = q0;
+    q[i][1] = q0 * st * cph;
+    q[i][2] = q0 * st * sph;
+    q[i][3] = q0 * c;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) Q[m] += q[i][m];
+  }
+  const R M = sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
+  const R b1 = -Q[1] / M, b2 = -Q[2] / M, b3 = -Q[3] / M;
+  const R gam = Q[0] / M;
+  const R aa = 1.0 / (1.0 + gam);
+  const R x = a.sqrts / M;
+  const double h = 0.5 * a.sqrts;
+  p[0][0] = h; p[0][1] = 0.0; p[0][2] = 0.0; p[0][3] = h;
+  p[1][0] = h; p[1][1] = 0.0; p[1][2] = 0.0; p[1][3] = -h;
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    const R bq = b1 * q[i][1] + b2 * q[i][2] + b3 * q[i][3];
+    p[i + 2][0] = x * (gam * q[i][0] + bq);
+    p[i + 2][1] = x * (q[i][1] + b1 * q[i][0] + aa * bq * b1);
+    p[i + 2][2] = x * (q[i][2] + b2 * q[i][0] + aa * bq * b2);
+    p[i + 2][3] = x * (q[i][3] + b3 * q[i][0] + aa * bq * b3);
+  }
+  w = a.w0;
+  if (!a.massive) return true;
+  // Newton solve of sum_i sqrt(m_i^2 + xi^2 E_i^2) = sqrt(s) on the values
+  double xiv = a.xi0;
+  bool ok = false;
+  for (int it = 0; it <= 50; ++it) {
+    double f = -a.sqrts, fp = 0.0;
+#pragma unroll
+    for (int i = 0; i < NF; ++i) {
+      const double E = val(p[i + 2][0]);
+      const double root = sqrt(a.m2[i] + xiv * xiv * E * E);
+      f += root;
+      fp += xiv * E * E / root;
+    }
+    if (fabs(f) <= 1e-14 * a.sqrts) {
+      ok = true;
+      break;
+    }
+    if (it == 50) break;
+    xiv -= f / fp;
+  }
+  R E[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) E[i] = p[i + 2][0];
+  const R xi = with_xi_derivative(xiv, E, a.m2, a, NF);
+  R prod = 1.0, den = 0.0;
+#pragma unroll
+  for (int i = 0; i < NF; ++i) {
+    const R k0 = sqrt(a.m2[i] + xi * xi * E[i] * E[i]);
+    const R kx = xi * p[i + 2][1], ky = xi * p[i + 2][2], kz = xi * p[i + 2][3];
+    const R kabs = sqrt(kx * kx + ky * ky + kz * kz);
+    prod = prod * (kabs / k0);
+    den = den + kabs * kabs / k0;
+    p[i + 2][0] = k0;
+    p[i + 2][1] = kx;
+    p[i + 2][2] = ky;
+    p[i + 2][3] = kz;
+  }
+  R xin = 1.0;
+#pragma unroll
+  for (int k = 0; k < 2 * NF - 3; ++k) xin = xin * xi;
+  w = a.w0 * xin * prod * a.sqrts / den;
+  if (!ok) w = __builtin_nan("");
+  return ok;
+}
+
+}  // namespace mg

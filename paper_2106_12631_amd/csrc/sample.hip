@@ -7,13 +7,10 @@
 // Slot s of an event uses block s/2; the 64-bit word is
 // x[2(s%2)] + 2^32 x[2(s%2)+1] and u = ((w >> 11) + 1/2) 2^-53.
 //
-// Phase space (Sec. IV.a/IV.b; Kleiss, Stirling, Ellis, CPC 40 (1986) 359):
-// four uniforms per final-state particle give an isotropic massless q_i
-// with energy -ln(r2 r3); the q_i are boosted to the rest frame of their sum
-// and scaled to sqrt(s); masses are introduced by a Newton solve for the
-// common scale xi of the three-momenta, in FP64.
+// Phase space: RAMBO (rambo.h) on the uniforms of each event.
 #include "common.h"
 #include "internal.h"
+#include "rambo.h"
 
 namespace mg {
 
@@ -53,87 +50,6 @@ __device__ __forceinline__ void event_uniforms(uint64_t seed, uint64_t ievt, dou
     u[2 * j] = bits_to_u(c0, c1);
     if (2 * j + 1 < NRND) u[2 * j + 1] = bits_to_u(c2, c3);
   }
-}
-
-// RAMBO for NF final-state particles.  p[0], p[1] are the incoming momenta
-// along +z and -z; returns false if the Newton solve did not converge.
-template <int NF>
-__device__ __forceinline__ bool rambo(const double (&r)[4 * NF], const RamboArgs& a,
-                                      double (&p)[NF + 2][4], double& w) {
-  const double twopi = 6.283185307179586476925286766559;
-  double q[NF][4];
-  double Q[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int i = 0; i < NF; ++i) {
-    const double c = 2.0 * r[4 * i] - 1.0;
-    const double st = sqrt(1.0 - c * c);
-    double sph, cph;
-    sincos(twopi * r[4 * i + 1], &sph, &cph);
-    const double q0 = -log(r[4 * i + 2] * r[4 * i + 3]);
-    q[i][0] = q0;
-    q[i][1] = q0 * st * cph;
-    q[i][2] = q0 * st * sph;
-    q[i][3] = q0 * c;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) Q[m] += q[i][m];
-  }
-  const double M = sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
-  const double b1 = -Q[1] / M, b2 = -Q[2] / M, b3 = -Q[3] / M;
-  const double gam = Q[0] / M;
-  const double aa = 1.0 / (1.0 + gam);
-  const double x = a.sqrts / M;
-  const double h = 0.5 * a.sqrts;
-  p[0][0] = h; p[0][1] = 0.0; p[0][2] = 0.0; p[0][3] = h;
-  p[1][0] = h; p[1][1] = 0.0; p[1][2] = 0.0; p[1][3] = -h;
-#pragma unroll
-  for (int i = 0; i < NF; ++i) {
-    const double bq = b1 * q[i][1] + b2 * q[i][2] + b3 * q[i][3];
-    p[i + 2][0] = x * (gam * q[i][0] + bq);
-    p[i + 2][1] = x * (q[i][1] + b1 * q[i][0] + aa * bq * b1);
-    p[i + 2][2] = x * (q[i][2] + b2 * q[i][0] + aa * bq * b2);
-    p[i + 2][3] = x * (q[i][3] + b3 * q[i][0] + aa * bq * b3);
-  }
-  w = a.w0;
-  if (!a.massive) return true;
-  // Newton solve of sum_i sqrt(m_i^2 + xi^2 E_i^2) = sqrt(s)
-  double xi = a.xi0;
-  bool ok = false;
-  for (int it = 0; it <= 50; ++it) {
-    double f = -a.sqrts, fp = 0.0;
-#pragma unroll
-    for (int i = 0; i < NF; ++i) {
-      const double E = p[i + 2][0];
-      const double root = sqrt(a.m2[i] + xi * xi * E * E);
-      f += root;
-      fp += xi * E * E / root;
-    }
-    if (fabs(f) <= 1e-14 * a.sqrts) {
-      ok = true;
-      break;
-    }
-    if (it == 50) break;
-    xi -= f / fp;
-  }
-  double prod = 1.0, den = 0.0;
-#pragma unroll
-  for (int i = 0; i < NF; ++i) {
-    const double E = p[i + 2][0];
-    const double k0 = sqrt(a.m2[i] + xi * xi * E * E);
-    const double kx = xi * p[i + 2][1], ky = xi * p[i + 2][2], kz = xi * p[i + 2][3];
-    const double kabs = sqrt(kx * kx + ky * ky + kz * kz);
-    prod *= kabs / k0;
-    den += kabs * kabs / k0;
-    p[i + 2][0] = k0;
-    p[i + 2][1] = kx;
-    p[i + 2][2] = ky;
-    p[i + 2][3] = kz;
-  }
-  double xin = 1.0;
-#pragma unroll
-  for (int k = 0; k < 2 * NF - 3; ++k) xin *= xi;
-  w = a.w0 * xin * prod * a.sqrts / den;
-  if (!ok) w = __builtin_nan("");
-  return ok;
 }
 
 template <int NRND>

@@ -247,6 +247,19 @@ def _ksum(legs, particles):
     return '{' + ', '.join(comps) + '}'
 
 
+def _coef_value(coef, amp):
+    c = complex(coef)
+    if c == 1:
+        return amp
+    if c == -1:
+        return f"-{amp}"
+    if c == 1j:
+        return f"times_i({amp})"
+    if c == -1j:
+        return f"-times_i({amp})"
+    return f"cx<T>{{(T){c.real!r}, (T){c.imag!r}}} * {amp}"
+
+
 def _coef_expr(coef, amp):
     c = complex(coef)
     if c == 1:
@@ -271,26 +284,26 @@ def _node_code(n, name, dn, parts):
     K = _ksum(n.legs, parts)
     if op[0] == 'vvv':
         a, b = op[1], op[2]
-        return (f"cx<T> {name}[4]; {{ const double KA[4] = {_ksum(a.legs, parts)}; "
-                f"const double KB[4] = {_ksum(b.legs, parts)}; "
+        return (f"cx<T> {name}[4]; {{ const R KA[4] = {_ksum(a.legs, parts)}; "
+                f"const R KB[4] = {_ksum(b.legs, parts)}; "
                 f"vvv_cur<T>({dn[0]}, KA, {dn[1]}, KB, c.gs, {name}); }}", FLOPS['vvv_cur'])
     if op[0] == 'vvvv':
         s = op[1]
-        return (f"cx<T> {name}[4]; {{ const double K[4] = {K}; "
+        return (f"cx<T> {name}[4]; {{ const R K[4] = {K}; "
                 f"vvvv_cur<{s}, T>({dn[0]}, {dn[1]}, {dn[2]}, K, c.gs2, {name}); }}",
                 FLOPS['vvvv_cur'])
     if op[0] == 'ffv_fout':
         f, vec = op[1], op[2]
         cl, cr = FFV[(f.flav, vec.flav)]
         m, wd = FERMION_MASS[f.flav]
-        return (f"cx<T> {name}[4]; {{ const double K[4] = {K}; "
+        return (f"cx<T> {name}[4]; {{ const R K[4] = {K}; "
                 f"ffv_cur_fout<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{m}, c.{wd}, {name}); }}",
                 FLOPS['ffv_cur_fout'])
     if op[0] == 'ffv_fin':
         vec, f = op[1], op[2]
         cl, cr = FFV[(f.flav, vec.flav)]
         m, wd = FERMION_MASS[f.flav]
-        return (f"cx<T> {name}[4]; {{ const double K[4] = {K}; "
+        return (f"cx<T> {name}[4]; {{ const R K[4] = {K}; "
                 f"ffv_cur_fin<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{m}, c.{wd}, {name}); }}",
                 FLOPS['ffv_cur_fin'])
     if op[0] == 'ffv_v':
@@ -298,10 +311,10 @@ def _node_code(n, name, dn, parts):
         cl, cr = FFV[(fo.flav, boson)]
         bm = BOSON_MASS[boson]
         if bm is None:
-            return (f"cx<T> {name}[4]; {{ const double K[4] = {K}; "
+            return (f"cx<T> {name}[4]; {{ const R K[4] = {K}; "
                     f"ffv_cur_v0<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, {name}); }}",
                     FLOPS['ffv_cur_v0'])
-        return (f"cx<T> {name}[4]; {{ const double K[4] = {K}; "
+        return (f"cx<T> {name}[4]; {{ const R K[4] = {K}; "
                 f"ffv_cur_vm<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{bm[0]}, c.{bm[1]}, {name}); }}",
                 FLOPS['ffv_cur_vm'])
     raise ValueError(op)
@@ -320,7 +333,7 @@ def _ext_code(n, name, npar):
     return f"cx<T> {name}[4]; {fn[0]}<T>({p}, {mass}, {hel}, {fn[1]}, {name});", FLOPS[routine]
 
 
-def emit_body(pd, coefs, order, bils, need, budget):
+def emit_body(pd, coefs, order, bils, need, budget, evict_ext=False):
     """Straight-line body of jamps() for one register budget (in live
     wavefunctions).  Wavefunctions are computed on first use; when the
     budget is full the live one whose next use is farthest is dropped
@@ -362,7 +375,7 @@ def emit_body(pd, coefs, order, bils, need, budget):
 
     def evict(pos, pinned):
         while len(live) >= budget:
-            cand = [x for x in live if x not in pinned and live[x][1].op[0] != 'ext']
+            cand = [x for x in live if x not in pinned and (evict_ext or live[x][1].op[0] != 'ext')]
             if not cand:
                 return
             victim = max(cand, key=lambda x: next_use(x, pos))
@@ -382,6 +395,8 @@ def emit_body(pd, coefs, order, bils, need, budget):
         name = base if v == 0 else f"{base}_{v}"
         if n.op[0] == 'ext':
             code, fl = _ext_code(n, name, npar)
+            if v > 0:
+                recomputes += 1
         else:
             if v > 0:  # opaque copy of one input defeats common-subexpression merging
                 L.append(f"  cx<T> o{n.idx}_{v}[4] = {{{dn[0]}[0], {dn[0]}[1], {dn[0]}[2], {dn[0]}[3]}}; "
@@ -416,7 +431,7 @@ def emit_body(pd, coefs, order, bils, need, budget):
         algo += fl
         execd += fl
         for kk, coef in sorted(cf.items()):
-            L.append(f"    J[{kk}] = J[{kk}] {_coef_expr(coef, 'a')};")
+            L.append(f"    jacc(J[{kk}], {_coef_value(coef, 'a')});")
             algo += FLOPS['jamp_acc']
             execd += FLOPS['jamp_acc']
         L.append("  }")
@@ -431,7 +446,12 @@ def emit_body(pd, coefs, order, bils, need, budget):
 # and the momenta stay live besides them.  'f32m' is the FP32 body used by
 # the kernel whose colour sum runs on the matrix cores (its operands need
 # registers too).
-BUDGET = {'f64': 12, 'f32': 36, 'f32m': 28}
+BUDGET = {'f64': 12, 'f32': 36, 'f32m': 28, 'd64': 5, 'd32': 9, 'f64l': 8}
+# processes whose FP64 body is also generated with the colour-flow amplitudes
+# held in LDS instead of registers
+LDS_PROCESSES = ('ggttgg',)
+# processes whose amplitudes are also generated on dual numbers (gradient kernel)
+DUAL_PROCESSES = ('eemumu', 'ggtt', 'ggttg')
 OPT_ITERS = 2500
 # amplitude terms between two scheduling fences (see fence() in helas.h)
 FENCE_EVERY = 4
@@ -466,17 +486,27 @@ def generate(name):
     w("};")
     w("")
     stats = {}
-    for prec, T in (('f64', 'double'), ('f32', 'float'), ('f32m', 'float')):
+    variants = [('f64', 'double', 'double', 'double'), ('f32', 'float', 'double', 'float'),
+                ('f32m', 'float', 'double', 'float')]
+    if name in LDS_PROCESSES:
+        variants += [('f64l', 'double', 'double', 'double')]
+    if name in DUAL_PROCESSES:
+        variants += [('d64', 'dual<double>', 'dual<double>', 'double'),
+                     ('d32', 'dual<float>', 'dual<double>', 'float')]
+    for prec, T, Rt, Ct in variants:
         budget = int(os.environ.get(f'MG_BUDGET_{prec.upper()}', BUDGET[prec]))
         order = order0
         if schedule_cost(order0, need, budget) > schedule_cost(order0, need, 10 ** 6):
             order, _ = optimise_order(order0, need, budget, iters=OPT_ITERS)
-        body, algo, execd, peak, rec = emit_body(pd, coefs, order, bils, need, budget)
+        body, algo, execd, peak, rec = emit_body(pd, coefs, order, bils, need, budget,
+                                                 evict_ext=False)
         stats[prec] = dict(flops_amp_per_hel=algo, flops_executed_per_hel=execd,
                            peak_live_wavefunctions=peak, recomputed=rec)
-        w(f"__device__ __forceinline__ void jamps_{prec}(double (&p)[{npar}][4], unsigned hcode,")
-        w(f"                                          const Couplings<{T}>& c, cx<{T}> (&J)[{ncol}]) {{")
+        jparam = (f"LdsJamps<{T}> J" if prec.endswith('l') else f"cx<{T}> (&J)[{ncol}]")
+        w(f"__device__ __forceinline__ void jamps_{prec}({Rt} (&p)[{npar}][4], unsigned hcode,")
+        w(f"                                          const Couplings<{Ct}>& c, {jparam}) {{")
         w(f"  using T = {T};")
+        w(f"  using R = {Rt};")
         for k in range(ncol):
             w(f"  J[{k}] = cx<T>{{(T)0, (T)0}};")
         L.extend(body)
