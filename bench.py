@@ -83,19 +83,38 @@ def run_gpu(mg, torch, proc, prec, seed, nevt, steps, warmup):
 
 
 def run_gradient(mg, torch, prec, nevt, steps, warmup, seed=4):
-    """Gradient workload: d(w |M|^2)/dr and d log w/dr for g g -> t t~ g."""
+    """Gradient workload: d(w |M|^2)/dr and d log w/dr for g g -> t t~ g,
+    timed beside the forward pass (RAMBO + SIGMAKIN) on the same uniforms."""
     eng = mg.MEEngine('ggttg', prec)
     rnd = eng.rng(seed, nevt)
-    for _ in range(warmup):
-        eng.adjoint(rnd, nevt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        grad, glogw, f = eng.adjoint(rnd, nevt)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return {"events_per_s": nevt * steps / wall, "ms_per_launch": wall / steps * 1e3,
-            "nonfinite": eng.count_nonfinite(grad)}
+    mom = eng.empty_mom(nevt)
+    wgt = torch.empty(nevt, dtype=torch.float64, device=eng.device)
+    me = torch.empty(nevt, dtype=torch.float64, device=eng.device)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    out = {}
+
+    def grad():
+        out['g'] = eng.adjoint(rnd, nevt)
+
+    def fwd():
+        eng.rambo(rnd, nevt, mom=mom, wgt=wgt)
+        eng.sigmakin(mom, nevt, me=me)
+
+    t_grad = timed(grad)
+    t_fwd = timed(fwd)
+    return {"events_per_s": nevt / t_grad, "ms_per_launch": t_grad * 1e3,
+            "forward_ms": t_fwd * 1e3, "gradient_over_forward": t_grad / t_fwd,
+            "nonfinite": eng.count_nonfinite(out['g'][0])}
 
 
 def main():

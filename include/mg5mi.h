@@ -147,10 +147,13 @@ int mg_sigmakin_hel(const mg_handle_t* h, const double* mom, int64_t nevt, doubl
  *   grad_rnd[j]  = gbar[i] * df/dr_j       (AoSoA like rnd; gbar NULL = 1)
  *   grad_logw[j] = d log w / dr_j          (optional, AoSoA like rnd)
  *   f[i]         = w |M|^2                 (optional)
- * Computed by forward-mode differentiation (one dual-number pass per
- * uniform) through RAMBO, the Newton rescaling (implicit-function theorem)
- * and the helicity amplitudes; FP64 for MG_FP64, FP32 amplitudes with FP64
- * RAMBO and sums otherwise.  Built for e+e- -> mu+mu-, g g -> t t~ and
+ * Computed in reverse mode: per helicity the amplitudes run forward, the
+ * colour sum gives the colour-flow adjoints 2 C J / den, and hand-written
+ * adjoints of the wavefunction and vertex routines carry them back to the
+ * final-state momenta; the RAMBO Jacobian (including the Newton rescaling,
+ * by the implicit-function theorem) comes from one dual-number pass per
+ * uniform.  FP64 for MG_FP64, FP32 amplitudes and adjoints with FP64 RAMBO,
+ * momentum adjoints and sums otherwise.  Built for e+e- -> mu+mu-, g g -> t t~ and
  * g g -> t t~ g; MG_ENOTSUP for g g -> t t~ g g. */
 int mg_adjoint(const mg_handle_t* h, const double* rnd, int64_t nevt, const double* gbar_or_null,
                double* grad_rnd, double* grad_logw_or_null, double* f_or_null, void* stream);

@@ -11,7 +11,8 @@ import os
 
 import torch
 
-__all__ = ['MEEngine', 'MEWeight', 'PROCESSES', 'PRECISIONS', 'lib', 'library_path']
+__all__ = ['MEEngine', 'MEWeight', 'PROCESSES', 'PRECISIONS', 'lib', 'library_path', 'engine',
+           'sample', 'sigmakin']
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 PROCESSES = {'eemumu': 0, 'ggtt': 1, 'ggttg': 2, 'ggttgg': 3}
@@ -248,3 +249,26 @@ class MEWeight(torch.autograd.Function):
         grad, _, _ = eng.adjoint(eng.events_rnd(r), nevt, gbar=gout.contiguous().to(torch.float64),
                                  want_logw=False, want_f=False)
         return eng.rnd_events(grad, nevt), None
+
+
+# ----------------------------------------------------------------------------- shortcuts
+_ENGINES = {}
+
+
+def engine(process='ggttgg', precision='fp64', device=None):
+    """A cached MEEngine per (process, precision, device) with default params."""
+    dev = torch.device('cuda', torch.cuda.current_device()) if device is None else torch.device(device)
+    key = (process, precision, str(dev))
+    if key not in _ENGINES:
+        _ENGINES[key] = MEEngine(process, precision, device=dev)
+    return _ENGINES[key]
+
+
+def sample(seed, nevt, process='ggttgg', offset=0, keep_rnd=True):
+    """Random numbers and RAMBO events: (rnd AoSoA or None, mom AoSoA, wgt)."""
+    return engine(process).sample(seed, nevt, offset=offset, keep_rnd=keep_rnd)
+
+
+def sigmakin(mom, nevt, wgt=None, process='ggttgg', precision='fp64'):
+    """|M|^2 per event for AoSoA momenta (and w |M|^2 if wgt is given)."""
+    return engine(process, precision).sigmakin(mom, nevt, wgt=wgt)

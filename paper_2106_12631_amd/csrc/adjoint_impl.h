@@ -2,80 +2,73 @@
 // uniforms r of one event, and of log w (the differentiable event weight of
 // a phase-space adaptation built on RAMBO and SIGMAKIN).
 //
-// Forward mode: for each of the 4 nparf uniforms the kernel seeds that
-// uniform's derivative, carries value and derivative through RAMBO (the
-// Newton rescaling by the implicit-function theorem) and through the
-// generated helicity amplitudes and colour sum (instantiated on dual
-// numbers), and reads df/dr_j and dw/dr_j off the result.  Per event this
-// costs 4 nparf dual passes, which is cheaper in registers than storing
-// every intermediate wavefunction for a reverse sweep.  The helicity sum and
-// /IDEN are in FP64 (dual<double>); the amplitudes in dual<double> or
-// dual<float> (mixed).
+// Reverse mode: per helicity the generated
+// code runs the amplitudes forward, forms the colour-flow adjoints
+// Jb = 2 C J / den from the colour sum, and sweeps back through the
+// amplitude terms and currents (helas_adj.h) to the final-state momenta,
+// accumulating d|M|^2/dp over helicities.  The momenta depend on the
+// uniforms only through RAMBO, whose Jacobian dp/dr_j (and dw/dr_j) comes
+// from one cheap dual-number RAMBO pass per uniform; then
+//   df/dr_j = (1/IDEN) (w sum_{leg,mu} d|M|^2/dp dp/dr_j + |M|^2 dw/dr_j).
+// The helicity sum, the momentum adjoints and /IDEN are in FP64; the
+// amplitudes and their adjoints in FP64 or FP32 (mixed).
 #pragma once
 #include "common.h"
+#include "helas_adj.h"
 #include "internal.h"
 #include "rambo.h"
 
 namespace mg {
 
-template <class P, int NF, typename TD>
+template <class P, int NF, typename T>
 __global__ void __launch_bounds__(64)
-    grad_kernel(const double* __restrict__ rnd, int64_t nevt, RamboArgs ra, HelList hl,
-                Couplings<base_t<TD>> c, double inv_iden, const double* __restrict__ gbar,
-                double* __restrict__ grad_rnd, double* __restrict__ grad_logw,
-                double* __restrict__ mew) {
+    adjoint_kernel(const double* __restrict__ rnd, int64_t nevt, RamboArgs ra, HelList hl,
+                   Couplings<T> c, double inv_iden, const double* __restrict__ gbar,
+                   double* __restrict__ grad_rnd, double* __restrict__ grad_logw,
+                   double* __restrict__ mew) {
   using D = dual<double>;
-  constexpr int NR = 4 * NF;
+  constexpr int NR = 4 * NF, NP = NF + 2;
   const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (i >= nevt) return;
   double r[NR];
 #pragma unroll
   for (int k = 0; k < NR; ++k) r[k] = rnd[aosoa_rnd(i, k, NR)];
+  double p[NP][4], w;
+  rambo<NF>(r, ra, p, w);
+  double pb[NP][4];
+#pragma unroll
+  for (int l = 0; l < NP; ++l)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) pb[l][m] = 0.0;
+  double me = 0.0;
+#pragma nounroll
+  for (int h = 0; h < hl.n; ++h) me += P::adjoint(p, hl.code[h], c, pb);
   const double g = gbar ? gbar[i] : 1.0;
-  double fval = 0.0;
 #pragma nounroll
   for (int j = 0; j < NR; ++j) {
-    D w;
-    {
-      D rd[NR], p[NF + 2][4];
+    D rd[NR], pd[NP][4], wd;
 #pragma unroll
-      for (int k = 0; k < NR; ++k) rd[k] = D(r[k], k == j ? 1.0 : 0.0);
-      rambo<NF>(rd, ra, p, w);
-    }
-    D me = 0.0;
-#pragma nounroll
-    for (int h = 0; h < hl.n; ++h) {
-      // RAMBO is re-run per helicity from opaque copies of the uniforms: it
-      // is cheap, and keeping the dual momenta live across the helicity loop
-      // is not.
-      D rq[NR];
+    for (int k = 0; k < NR; ++k) rd[k] = D(r[k], k == j ? 1.0 : 0.0);
+    rambo<NF>(rd, ra, pd, wd);
+    double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < NR; ++k) {
-        double rv = r[k];
-        opaque(rv);
-        rq[k] = D(rv, k == j ? 1.0 : 0.0);
-      }
-      D p[NF + 2][4], wq;
-      rambo<NF>(rq, ra, p, wq);
-      cx<TD> J[P::NCOL];
-      P::jamps(p, hl.code[h], c, J);
-      me += D(P::colour_sum(J));
-    }
-    const D f = me * inv_iden * w;
-    grad_rnd[aosoa_rnd(i, j, NR)] = g * f.d;
-    if (grad_logw) grad_logw[aosoa_rnd(i, j, NR)] = w.d / w.v;
-    fval = f.v;
+    for (int l = 2; l < NP; ++l)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) s += pb[l][m] * pd[l][m].d;
+    const double df = inv_iden * (w * s + me * wd.d);
+    grad_rnd[aosoa_rnd(i, j, NR)] = g * df;
+    if (grad_logw) grad_logw[aosoa_rnd(i, j, NR)] = wd.d / wd.v;
   }
-  if (mew) mew[i] = fval;
+  if (mew) mew[i] = me * inv_iden * w;
 }
 
-template <class P, int NF, typename TD>
-int grad_launch(const MeArgs& a, const RamboArgs& ra, const Couplings<base_t<TD>>& c,
-                const double* rnd, int64_t nevt, const double* gbar, double* grad_rnd,
-                double* grad_logw, double* mew, hipStream_t s) {
+template <class P, int NF, typename T>
+int adjoint_launch(const MeArgs& a, const RamboArgs& ra, const Couplings<T>& c, const double* rnd,
+                   int64_t nevt, const double* gbar, double* grad_rnd, double* grad_logw,
+                   double* mew, hipStream_t s) {
   const unsigned g = (unsigned)((nevt + 63) / 64);
-  grad_kernel<P, NF, TD><<<g, 64, 0, s>>>(rnd, nevt, ra, a.hel, c, a.inv_iden, gbar, grad_rnd,
-                                          grad_logw, mew);
+  adjoint_kernel<P, NF, T><<<g, 64, 0, s>>>(rnd, nevt, ra, a.hel, c, a.inv_iden, gbar, grad_rnd,
+                                            grad_logw, mew);
   return 0;
 }
 

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "helas.h"
+#include "helas_adj.h"
 
 namespace mg {
 

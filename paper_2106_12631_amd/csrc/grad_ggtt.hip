@@ -1,31 +1,23 @@
-// Gradient kernels for ggtt: the generated amplitudes on dual numbers
-// (jamps_d64: FP64, jamps_d32: FP32 amplitudes) wrapped for adjoint_impl.h.
+// Gradient kernels for ggtt (adjoint_impl.h): the generated reverse-mode
+// code (adjoint_a64: FP64, adjoint_a32: FP32 amplitudes).
 #include "adjoint_impl.h"
 
 namespace mg {
 #include "generated/ggtt.inc"
 
-struct G64_ggtt {
-  static constexpr int NCOL = gen_ggtt::NCOL;
-  __device__ static __forceinline__ void jamps(dual<double> (&p)[gen_ggtt::NPAR][4], unsigned h,
-                                               const Couplings<double>& c,
-                                               cx<dual<double>> (&J)[NCOL]) {
-    gen_ggtt::jamps_d64(p, h, c, J);
-  }
-  __device__ static __forceinline__ dual<double> colour_sum(const cx<dual<double>> (&J)[NCOL]) {
-    return gen_ggtt::colour_sum<dual<double>>(J);
+struct A64_ggtt {
+  __device__ static __forceinline__ double adjoint(double (&p)[gen_ggtt::NPAR][4], unsigned h,
+                                                   const Couplings<double>& c,
+                                                   double (&pb)[gen_ggtt::NPAR][4]) {
+    return gen_ggtt::adjoint_a64(p, h, c, pb);
   }
 };
 
-struct G32_ggtt {
-  static constexpr int NCOL = gen_ggtt::NCOL;
-  __device__ static __forceinline__ void jamps(dual<double> (&p)[gen_ggtt::NPAR][4], unsigned h,
-                                               const Couplings<float>& c,
-                                               cx<dual<float>> (&J)[NCOL]) {
-    gen_ggtt::jamps_d32(p, h, c, J);
-  }
-  __device__ static __forceinline__ dual<float> colour_sum(const cx<dual<float>> (&J)[NCOL]) {
-    return gen_ggtt::colour_sum<dual<float>>(J);
+struct A32_ggtt {
+  __device__ static __forceinline__ double adjoint(double (&p)[gen_ggtt::NPAR][4], unsigned h,
+                                                   const Couplings<float>& c,
+                                                   double (&pb)[gen_ggtt::NPAR][4]) {
+    return gen_ggtt::adjoint_a32(p, h, c, pb);
   }
 };
 
@@ -33,10 +25,10 @@ int launch_grad_ggtt(int prec, const MeArgs& a, const RamboArgs& ra, const doubl
                    const double* gbar, double* grad_rnd, double* grad_logw, double* mew,
                    hipStream_t s) {
   if (prec == 0)
-    return grad_launch<G64_ggtt, 2, dual<double>>(a, ra, a.c64, rnd, nevt, gbar, grad_rnd,
-                                                  grad_logw, mew, s);
-  return grad_launch<G32_ggtt, 2, dual<float>>(a, ra, a.c32, rnd, nevt, gbar, grad_rnd, grad_logw,
-                                               mew, s);
+    return adjoint_launch<A64_ggtt, 2, double>(a, ra, a.c64, rnd, nevt, gbar, grad_rnd, grad_logw,
+                                                mew, s);
+  return adjoint_launch<A32_ggtt, 2, float>(a, ra, a.c32, rnd, nevt, gbar, grad_rnd, grad_logw,
+                                             mew, s);
 }
 
 }  // namespace mg

@@ -188,35 +188,9 @@ __device__ __forceinline__ void fence(R (&p)[N][4]) {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-// Colour-flow amplitudes: accumulated in registers (cx<T>&) or in this
-// lane's slots of an LDS array (LdsJamps, stride 64 lanes).  The LDS
-// accesses are volatile so that the compiler keeps them in LDS instead of
-// forwarding them back into registers.
+// Colour-flow amplitude accumulation (the generated code's jamp += c amp)
 template <typename T>
 __device__ __forceinline__ void jacc(cx<T>& j, cx<T> v) { j = j + v; }
-
-template <typename T>
-struct LdsRef {
-  T* p;  // real part; imaginary part at p + 64
-  __device__ __forceinline__ cx<T> get() const {
-    volatile T* v = p;
-    return cx<T>{v[0], v[64]};
-  }
-  __device__ __forceinline__ LdsRef& operator=(cx<T> x) {
-    volatile T* v = p;
-    v[0] = x.r;
-    v[64] = x.i;
-    return *this;
-  }
-};
-template <typename T>
-__device__ __forceinline__ void jacc(LdsRef<T> j, cx<T> v) { j = j.get() + v; }
-
-template <typename T>
-struct LdsJamps {
-  T* base;  // &lds[0][0][lane]: layout [flow][re/im][64 lanes]
-  __device__ __forceinline__ LdsRef<T> operator[](int k) const { return LdsRef<T>{base + 128 * k}; }
-};
 
 // ---------------------------------------------------------------------------
 // external wavefunctions

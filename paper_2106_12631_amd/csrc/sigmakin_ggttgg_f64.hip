@@ -19,20 +19,11 @@ struct P_ggttgg {
   __device__ static __forceinline__ T colour_sum(const cx<T> (&J)[NCOL]) {
     return gen_ggttgg::colour_sum<T>(J);
   }
-  __device__ static __forceinline__ void jamps_lds(double (&p)[NPAR][4], unsigned h,
-                                                   const Couplings<double>& c,
-                                                   LdsJamps<double> J) {
-    gen_ggttgg::jamps_f64l(p, h, c, J);
-  }
 };
 
 int launch_sigmakin_ggttgg_f64(const MeArgs& a, const double* mom, int64_t nevt, double* me,
                               const double* wgt, double* evtw, double* mehel, hipStream_t s) {
-#ifdef MG_FP64_REGISTER_JAMPS
   return sigmakin_launch<P_ggttgg, double, 64>(a, a.c64, mom, nevt, me, wgt, evtw, mehel, s);
-#else
-  return sigmakin_lds_launch<P_ggttgg>(a, mom, nevt, me, wgt, evtw, mehel, s);
-#endif
 }
 
 }  // namespace mg

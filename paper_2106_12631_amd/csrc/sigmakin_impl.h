@@ -50,52 +50,6 @@ __global__ void __launch_bounds__(BS)
   if (evtw) evtw[i] = m * wgt[i];
 }
 
-// FP64 with the colour-flow amplitudes held in LDS (one wave per block, each
-// lane owning its [flow][re/im] slots), which leaves the registers to the
-// wavefunctions; the colour sum reads them back once per helicity.
-template <class P>
-__global__ void __launch_bounds__(64)
-    sigmakin_lds_kernel(const double* __restrict__ mom, int64_t nevt, double* __restrict__ me,
-                        const double* __restrict__ wgt, double* __restrict__ evtw,
-                        double* __restrict__ mehel, HelList hl, Couplings<double> c,
-                        double inv_iden) {
-  __shared__ double jl[P::NCOL * 128];
-  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (i >= nevt) return;
-  const LdsJamps<double> J{&jl[threadIdx.x]};
-  double acc = 0.0;
-#pragma nounroll
-  for (int k = 0; k < hl.n; ++k) {
-    int64_t iq = i;
-    asm volatile("" : "+v"(iq));
-    double q[P::NPAR][4];
-    load_event<P>(mom, iq, q);
-    P::jamps_lds(q, hl.code[k], c, J);
-    cx<double> Jr[P::NCOL];
-#pragma unroll
-    for (int m = 0; m < P::NCOL; ++m) Jr[m] = J[m].get();
-    const double v = P::template colour_sum<double>(Jr);
-    if (mehel) mehel[(int64_t)hl.code[k] * nevt + i] = v;
-    acc += v;
-  }
-  const double m = acc * inv_iden;
-  if (me) me[i] = m;
-  if (evtw) evtw[i] = m * wgt[i];
-}
-
-template <class P>
-int sigmakin_lds_launch(const MeArgs& a, const double* mom, int64_t nevt, double* me,
-                        const double* wgt, double* evtw, double* mehel, hipStream_t s) {
-  const unsigned g = (unsigned)((nevt + 63) / 64);
-  HelList hl = a.hel;
-  if (mehel) {
-    hl.n = 1 << P::NPAR;
-    for (int k = 0; k < hl.n; ++k) hl.code[k] = (uint8_t)k;
-  }
-  sigmakin_lds_kernel<P><<<g, 64, 0, s>>>(mom, nevt, me, wgt, evtw, mehel, hl, a.c64, a.inv_iden);
-  return 0;
-}
-
 // Mixed precision: FP32 amplitudes, colour sum on the matrix cores (CS =
 // ColourMfmaF32 or ColourMfmaBf16), FP64 helicity sum.  One wave per block;
 // lanes past nevt compute a copy of the last event and store nothing, so

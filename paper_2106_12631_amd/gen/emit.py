@@ -16,7 +16,7 @@ fused multiply-add = 2, divide, square root = 1).
 import json
 import os
 
-from .diagrams import BOSON_MASS, FERMION_MASS, FFV, ProcessDiagrams, colour_matrix, IN
+from .diagrams import BOSON_MASS, FERMION_MASS, FFV, ProcessDiagrams, colour_matrix, IN, OUT
 
 IDEN = {'eemumu': 4, 'ggtt': 256, 'ggttg': 256, 'ggttgg': 512}
 
@@ -441,17 +441,257 @@ def emit_body(pd, coefs, order, bils, need, budget, evict_ext=False):
     return L, algo, execd, peak, recomputes
 
 
+
+# ----------------------------------------------------------------------------
+# reverse mode
+# ----------------------------------------------------------------------------
+ADJ_FLOPS = {  # algorithmic flops of the adjoint routines of helas_adj.h
+    'ffv_amp': 118 + 64 + 160, 'mdot_i': 64, 'bilinear': 160,
+    'ffv_cur_v0': 16 + 160 + 16 + 12, 'ffv_cur_vm': 88 + 200 + 16 + 60,
+    'ffv_cur_fin': 200 + 60 + 120, 'ffv_cur_fout': 200 + 60 + 120,
+    'vvv_cur': 260, 'vvvv_cur': 230, 'ext': 4 * 110, 'jbar': 0,
+}
+
+
+def _legs_of(n):
+    if isinstance(n, Bil):
+        return n.fout.legs | n.fin.legs
+    return n.legs
+
+
+def emit_adjoint_body(pd, coefs, order, bils, need, budget):
+    """Reverse sweep of jamps() for one helicity: the colour-flow adjoints
+    Jb (already formed) are propagated back through the amplitude terms (in
+    reverse order) and the wavefunctions (each once all its consumers are
+    done) to the external momenta, accumulated into pb[leg][mu] for the
+    final-state legs.  Forward values are recomputed from the externals
+    under the same live-wavefunction budget as the forward code (Belady
+    eviction).  Wavefunctions whose legs are all initial-state carry no
+    momentum dependence and are not differentiated.  Returns (lines,
+    executed flops)."""
+    import bisect
+    parts = pd.particles
+    npar = pd.npar
+
+    def final(n):
+        return any(parts[l][1] == OUT for l in _legs_of(n))
+
+    def closure(nodes):
+        out, stack = {}, list(nodes)
+        while stack:
+            n = stack.pop()
+            if n.idx in out:
+                continue
+            out[n.idx] = n
+            stack.extend(_deps(n))
+        return out
+
+    first_use = {}
+    nodes = {}
+    for pos, k in enumerate(order):
+        for x, n in closure(need(k)).items():
+            first_use.setdefault(x, pos)
+            nodes[x] = n
+    # reverse step list: ('amp', pos) then ('node', n) for the nodes first
+    # used at pos, larger leg sets (consumers) first
+    steps = []
+    for pos in reversed(range(len(order))):
+        steps.append(('amp', pos, list(need(order[pos]))))
+        born = [nodes[x] for x, f in first_use.items() if f == pos]
+        born.sort(key=lambda n: (-len(_legs_of(n)), -n.idx))
+        for n in born:
+            if final(n):
+                steps.append(('node', n, _deps(n)))
+    uses_at = {}
+    for si, st in enumerate(steps):
+        for x in closure(st[2]):
+            uses_at.setdefault(x, []).append(si)
+    INF = 10 ** 9
+
+    def next_use(x, si):
+        lst = uses_at.get(x, [])
+        i = bisect.bisect_left(lst, si)
+        return lst[i] if i < len(lst) else INF
+
+    live = {}
+    version = {}
+    L = []
+    execd = 0
+
+    def evict(si, pinned):
+        while len(live) >= budget:
+            cand = [x for x in live if x not in pinned and live[x][1].op[0] != 'ext']
+            if not cand:
+                return
+            del live[max(cand, key=lambda x: next_use(x, si))]
+
+    def ensure(n, si, pinned):
+        nonlocal execd
+        if n.idx in live:
+            return live[n.idx][0]
+        deps = _deps(n)
+        pin = set(pinned) | {n.idx} | {d.idx for d in deps}
+        dn = [ensure(d, si, pin) for d in deps]
+        evict(si, pin)
+        v = version.get(n.idx, 0)
+        version[n.idx] = v + 1
+        base = f"rb{n.idx - 10 ** 6}" if isinstance(n, Bil) else f"rw{n.idx}"
+        name = f"{base}_{v}"
+        if n.op[0] == 'ext':
+            code, fl = _ext_code(n, name, npar)
+        else:
+            if v > 0:
+                L.append(f"  cx<T> o{name}[4] = {{{dn[0]}[0], {dn[0]}[1], {dn[0]}[2], {dn[0]}[3]}}; "
+                         f"opaque4(o{name});")
+                dn = [f"o{name}"] + dn[1:]
+            code, fl = _node_code(n, name, dn, parts)
+        L.append("  " + code)
+        execd += fl
+        live[n.idx] = (name, n)
+        return name
+
+    declared = set()
+
+    def bar(n):
+        """Name of n's adjoint accumulator (declared on first use), or a sink."""
+        if not final(n):
+            return None
+        nm = f"wb{n.idx - 10 ** 6}b" if isinstance(n, Bil) else f"wb{n.idx}"
+        if n.idx not in declared:
+            declared.add(n.idx)
+            L.append(f"  cx<T> {nm}[4] = {{{{(T)0, (T)0}}, {{(T)0, (T)0}}, {{(T)0, (T)0}}, {{(T)0, (T)0}}}};")
+        return nm
+
+    sink_count = [0]
+
+    def acc(n):
+        nm = bar(n)
+        if nm is None:
+            sink_count[0] += 1
+            nm = f"sink{sink_count[0]}"
+            L.append(f"  cx<T> {nm}[4] = {{}};")
+        return nm
+
+    def kback(legs, kname):
+        for l in sorted(legs):
+            if parts[l][1] == OUT:
+                L.append(f"  for (int m = 0; m < 4; ++m) pb[{l}][m] -= (double){kname}[m];")
+
+    for si, st in enumerate(steps):
+        if si % FENCE_EVERY == 0:
+            L.append("  fence(p);")
+        if st[0] == 'amp':
+            pos, nd = st[1], st[2]
+            k = order[pos]
+            d = pd.diagrams[k]
+            pin = {n.idx for n in nd}
+            names = [ensure(n, si, pin) for n in nd]
+            terms = []
+            for kk, coef in sorted(coefs[k].items()):
+                terms.append(_coef_expr(complex(coef).conjugate(), f"Jb[{kk}]"))
+            expr = " ".join(terms)
+            expr = expr[2:] if expr.startswith('+ ') else expr
+            an = [acc(x) for x in nd]
+            L.append(f"  {{ const cx<T> ab = {expr};")
+            if len(nd) == 2:
+                L.append(f"    adj_mdot_i({names[0]}, {names[1]}, ab, {an[0]}, {an[1]}); }}")
+                execd += ADJ_FLOPS['mdot_i']
+            else:
+                cl, cr = FFV[(d.fin.flav, d.vec.flav)]
+                L.append(f"    adj_ffv_amp<T>({names[0]}, {names[1]}, {names[2]}, c.{cl}, c.{cr}, ab, "
+                         f"{an[0]}, {an[1]}, {an[2]}); }}")
+                execd += ADJ_FLOPS['ffv_amp']
+        else:
+            n, deps = st[1], st[2]
+            pin = {n.idx} | {x.idx for x in deps}
+            dn = [ensure(x, si, pin) for x in deps]
+            wb = bar(n)
+            op = n.op
+            if isinstance(n, Bil):
+                cl, cr = n.couplings
+                L.append(f"  adj_bilinear<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, {wb}, "
+                         f"{acc(deps[0])}, {acc(deps[1])});")
+                execd += ADJ_FLOPS['bilinear']
+                continue
+            if op[0] == 'ext':
+                l, routine = op[1], op[2]
+                if parts[l][1] != OUT:
+                    continue
+                hel = f"((hcode >> {npar - 1 - l}) & 1u) ? 1 : -1"
+                if routine in ('vec_in', 'vec_out'):
+                    L.append(f"  adj_ext_vector<T>(p[{l}], {hel}, "
+                             f"{'false' if routine == 'vec_in' else 'true'}, {wb}, pb[{l}]);")
+                else:
+                    mass = {'t': 'c.mt'}.get(n.flav, '0.0')
+                    fn = {'ubar': ('adj_ext_u', 'true'), 'u': ('adj_ext_u', 'false'),
+                          'v': ('adj_ext_v', 'false'), 'vbar': ('adj_ext_v', 'true')}[routine]
+                    L.append(f"  {fn[0]}<T>(p[{l}], {mass}, {hel}, {fn[1]}, {wb}, pb[{l}]);")
+                execd += ADJ_FLOPS['ext']
+                continue
+            K = _ksum(n.legs, parts)
+            accs = {x.idx: acc(x) for x in deps}
+            L.append("  {")
+            if op[0] == 'vvv':
+                a, b = op[1], op[2]
+                L.append(f"    const R KA[4] = {_ksum(a.legs, parts)}; const R KB[4] = {_ksum(b.legs, parts)};")
+                L.append("    T KAb[4] = {(T)0, (T)0, (T)0, (T)0}, KBb[4] = {(T)0, (T)0, (T)0, (T)0};")
+                L.append(f"    adj_vvv_cur<T>({dn[0]}, KA, {dn[1]}, KB, c.gs, {wb}, {accs[a.idx]}, KAb, "
+                         f"{accs[b.idx]}, KBb);")
+                for legs, kn in ((a.legs, 'KAb'), (b.legs, 'KBb')):
+                    for l in sorted(legs):
+                        if parts[l][1] == OUT:
+                            L.append(f"    for (int m = 0; m < 4; ++m) pb[{l}][m] -= (double){kn}[m];")
+                execd += ADJ_FLOPS['vvv_cur']
+            else:
+                L.append(f"    const R K[4] = {K}; T Kb[4] = {{(T)0, (T)0, (T)0, (T)0}};")
+                if op[0] == 'vvvv':
+                    sgn, x, y, z = op[1], op[2], op[3], op[4]
+                    L.append(f"    adj_vvvv_cur<{sgn}, T>({dn[0]}, {dn[1]}, {dn[2]}, K, c.gs2, {wb}, "
+                             f"{accs[x.idx]}, {accs[y.idx]}, {accs[z.idx]}, Kb);")
+                    execd += ADJ_FLOPS['vvvv_cur']
+                elif op[0] == 'ffv_fout':
+                    f, vec = op[1], op[2]
+                    cl, cr = FFV[(f.flav, vec.flav)]
+                    m, wd = FERMION_MASS[f.flav]
+                    L.append(f"    adj_ffv_cur_fout<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{m}, c.{wd}, "
+                             f"{wb}, {accs[f.idx]}, {accs[vec.idx]}, Kb);")
+                    execd += ADJ_FLOPS['ffv_cur_fout']
+                elif op[0] == 'ffv_fin':
+                    vec, f = op[1], op[2]
+                    cl, cr = FFV[(f.flav, vec.flav)]
+                    m, wd = FERMION_MASS[f.flav]
+                    L.append(f"    adj_ffv_cur_fin<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{m}, c.{wd}, "
+                             f"{wb}, {accs[vec.idx]}, {accs[f.idx]}, Kb);")
+                    execd += ADJ_FLOPS['ffv_cur_fin']
+                elif op[0] == 'ffv_v':
+                    fo, fi, boson = op[1], op[2], op[3]
+                    cl, cr = FFV[(fo.flav, boson)]
+                    bm = BOSON_MASS[boson]
+                    if bm is None:
+                        L.append(f"    adj_ffv_cur_v0<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, {wb}, "
+                                 f"{accs[fo.idx]}, {accs[fi.idx]}, Kb);")
+                        execd += ADJ_FLOPS['ffv_cur_v0']
+                    else:
+                        L.append(f"    adj_ffv_cur_vm<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{bm[0]}, "
+                                 f"c.{bm[1]}, {wb}, {accs[fo.idx]}, {accs[fi.idx]}, Kb);")
+                        execd += ADJ_FLOPS['ffv_cur_vm']
+                else:
+                    raise ValueError(op)
+                for l in sorted(n.legs):
+                    if parts[l][1] == OUT:
+                        L.append(f"    for (int m = 0; m < 4; ++m) pb[{l}][m] -= (double)Kb[m];")
+            L.append("  }")
+    return L, execd
+
+
 # register budget in live wavefunctions (4 complex each) per precision:
 # FP64 wavefunctions take 16 VGPRs, FP32 ones 8; the colour-flow amplitudes
 # and the momenta stay live besides them.  'f32m' is the FP32 body used by
 # the kernel whose colour sum runs on the matrix cores (its operands need
 # registers too).
-BUDGET = {'f64': 12, 'f32': 36, 'f32m': 28, 'd64': 5, 'd32': 9, 'f64l': 8}
-# processes whose FP64 body is also generated with the colour-flow amplitudes
-# held in LDS instead of registers
-LDS_PROCESSES = ('ggttgg',)
-# processes whose amplitudes are also generated on dual numbers (gradient kernel)
-DUAL_PROCESSES = ('eemumu', 'ggtt', 'ggttg')
+BUDGET = {'f64': 12, 'f32': 36, 'f32m': 28, 'a64': 8, 'a32': 12}
+# processes with a generated reverse-mode (adjoint) body for the gradient kernel
+GRAD_PROCESSES = ('eemumu', 'ggtt', 'ggttg')
 OPT_ITERS = 2500
 # amplitude terms between two scheduling fences (see fence() in helas.h)
 FENCE_EVERY = 4
@@ -488,11 +728,6 @@ def generate(name):
     stats = {}
     variants = [('f64', 'double', 'double', 'double'), ('f32', 'float', 'double', 'float'),
                 ('f32m', 'float', 'double', 'float')]
-    if name in LDS_PROCESSES:
-        variants += [('f64l', 'double', 'double', 'double')]
-    if name in DUAL_PROCESSES:
-        variants += [('d64', 'dual<double>', 'dual<double>', 'double'),
-                     ('d32', 'dual<float>', 'dual<double>', 'float')]
     for prec, T, Rt, Ct in variants:
         budget = int(os.environ.get(f'MG_BUDGET_{prec.upper()}', BUDGET[prec]))
         order = order0
@@ -502,7 +737,7 @@ def generate(name):
                                                  evict_ext=False)
         stats[prec] = dict(flops_amp_per_hel=algo, flops_executed_per_hel=execd,
                            peak_live_wavefunctions=peak, recomputed=rec)
-        jparam = (f"LdsJamps<{T}> J" if prec.endswith('l') else f"cx<{T}> (&J)[{ncol}]")
+        jparam = f"cx<{T}> (&J)[{ncol}]"
         w(f"__device__ __forceinline__ void jamps_{prec}({Rt} (&p)[{npar}][4], unsigned hcode,")
         w(f"                                          const Couplings<{Ct}>& c, {jparam}) {{")
         w(f"  using T = {T};")
@@ -536,6 +771,42 @@ def generate(name):
         cs_flops += 2 * (2 * len(terms_r) - 1) + 4
     w(f"  return me * (T){1.0 / cden!r};")
     w("}")
+    A = []
+    if name in GRAD_PROCESSES:
+        for prec, T, Ct in (('a64', 'double', 'double'), ('a32', 'float', 'float')):
+            budget = int(os.environ.get(f'MG_BUDGET_{prec.upper()}', BUDGET[prec]))
+            order = order0
+            if schedule_cost(order0, need, budget) > schedule_cost(order0, need, 10 ** 6):
+                order, _ = optimise_order(order0, need, budget, iters=OPT_ITERS)
+            fwd, algo, execd, peak, rec = emit_body(pd, coefs, order, bils, need, budget)
+            rev, rexec = emit_adjoint_body(pd, coefs, order, bils, need, budget)
+            stats[prec] = dict(flops_forward_executed_per_hel=execd, flops_reverse_executed_per_hel=rexec)
+            A.append(f"// reverse mode: returns the colour-summed |M|^2 of helicity hcode and adds")
+            A.append(f"// its gradient with respect to the momenta of the final-state legs to pb")
+            A.append(f"__device__ __forceinline__ double adjoint_{prec}(double (&p)[{npar}][4], unsigned hcode,")
+            A.append(f"                                            const Couplings<{Ct}>& c,")
+            A.append(f"                                            double (&pb)[{npar}][4]) {{")
+            A.append(f"  using T = {T};")
+            A.append(f"  using R = double;")
+            A.append(f"  cx<T> J[{ncol}];")
+            for k in range(ncol):
+                A.append(f"  J[{k}] = cx<T>{{(T)0, (T)0}};")
+            A.append("  {")
+            A.extend(fwd)
+            A.append("  }")
+            A.append(f"  const T me = colour_sum<T>(J);")
+            A.append(f"  cx<T> Jb[{ncol}];")
+            for i in range(ncol):
+                tr = " + ".join(f"(T){cnum[i][j]} * J[{j}].r" for j in range(ncol) if cnum[i][j])
+                ti = " + ".join(f"(T){cnum[i][j]} * J[{j}].i" for j in range(ncol) if cnum[i][j])
+                A.append(f"  Jb[{i}] = cx<T>{{(T){2.0 / cden!r} * ({tr}), (T){2.0 / cden!r} * ({ti})}};")
+            A.append("  {")
+            A.extend(rev)
+            A.append("  }")
+            A.append("  return (double)me;")
+            A.append("}")
+            A.append("")
+    L.extend(A)
     w(f"}}  // namespace gen_{name}")
     cs_flops += 1
     meta = {

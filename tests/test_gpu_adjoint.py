@@ -5,14 +5,16 @@ f(r) = w(r) |M|^2(p(r)) per event, differentiated with respect to the 12
 uniforms of g g -> t t~ g (the gradient workload: seed 4, 2^18 events, the
 finite-difference check on the first 1024 events, h = 1e-6).
 Tolerances:
+* f = w |M|^2 vs the oracle: 1e-12 relative, plus RAMBO's rounding bound
+  128 eps gamma^2 (each side computes its own momenta);
 * FP64 gradient vs the oracle's autograd gradient, per event normwise:
-  1e-10 (both exact derivatives in FP64; RAMBO's boost amplifies rounding);
-  d log w / dr (dimensionless) normwise relative to max(|d log w / dr|, 1),
-  since the weight is constant for massless and for two-body final states
-  and both sides then hold rounding noise only;
-* FP64 gradient vs central differences: 1e-6 normwise (FD truncation
-  ~h^2 f''' and rounding ~eps f / h), events with a uniform within 10 h of 0
-  or 1 excluded and counted;
+  1e-10 plus 128 eps gamma^3 (the derivative of the boost adds a factor
+  gamma); d log w / dr (dimensionless) normwise relative to
+  max(|d log w / dr|, 1), since the weight is constant for massless and for
+  two-body final states and both sides then hold rounding noise only;
+* FP64 gradient vs central differences with step h (fourth-order stencil):
+  1e-6 normwise (truncation ~h^4 f^(5), rounding ~eps f / h), events with a
+  uniform within 10 h of 0 or 1 excluded and counted;
 * FP32-amplitude gradient vs the FP64 one: max and median reported; the
   median must stay below 1e-5.
 """
@@ -23,6 +25,7 @@ import pytest
 import torch
 
 from oracle import me as orc
+from rounding import EPS, boost_gamma
 
 pytestmark = pytest.mark.gpu
 SEED = 4
@@ -74,9 +77,12 @@ def test_gradient_vs_oracle_autograd(mg, proc, n):
     werr = normwise_unit(gw, gw_orc)
     say(proc, 'f rel', ferr, 'grad max', float(gerr.max()), 'median', float(gerr.median()),
         'logw max', float(werr.max()))
-    assert ferr <= 1e-12
-    assert float(gerr.max()) <= 1e-10
-    assert float(werr.max()) <= 1e-10
+    gam = boost_gamma(r)
+    frel = (f.cpu() - f_orc).abs() / f_orc.abs()
+    assert (frel <= 1e-12 + 128 * EPS * gam ** 2).all()
+    gtol = 1e-10 + 128 * EPS * gam ** 3
+    assert (gerr <= gtol).all()
+    assert (werr <= gtol).all()
     # gbar scales each event's gradient
     gbar = torch.linspace(0.5, 2.0, n, dtype=torch.float64, device=e.device)
     grad2, _, _ = e.adjoint(e.events_rnd(r), n, gbar=gbar, want_logw=False, want_f=False)
@@ -85,18 +91,21 @@ def test_gradient_vs_oracle_autograd(mg, proc, n):
 
 
 def _fd_gradient(e, r, h):
-    """Central differences of f = w |M|^2 with the FP64 RAMBO and SIGMAKIN kernels."""
+    """Central differences of f = w |M|^2 with the FP64 RAMBO and SIGMAKIN
+    kernels, fourth-order stencil on f(r -+ 2h), f(r -+ h).  The two-point
+    difference carries a truncation error h^2 f'''/6 that reaches 3e-5
+    relative on events with a nearly collinear gluon; this one's is O(h^4)."""
     n, nr = r.shape
     out = torch.zeros(n, nr, dtype=torch.float64)
     for j in range(nr):
-        vals = []
-        for s in (1.0, -1.0):
+        vals = {}
+        for s in (-2, -1, 1, 2):
             rr = r.clone()
             rr[:, j] += s * h
             mom, wgt = e.rambo(e.events_rnd(rr), n)
             _, evtw = e.sigmakin(mom, n, wgt=wgt)
-            vals.append(evtw.cpu())
-        out[:, j] = (vals[0] - vals[1]) / (2 * h)
+            vals[s] = evtw.cpu()
+        out[:, j] = (vals[-2] - 8 * vals[-1] + 8 * vals[1] - vals[2]) / (12 * h)
     return out
 
 
@@ -160,7 +169,7 @@ def test_gradient_full_size(mg):
     gg = e.rnd_events(grad, n)[idx].cpu()
     rs = torch.cat([orc.sample('ggttg', SEED, i, 1)[0] for i in idx])
     _, g_orc, _ = orc.event_weight_and_grad('ggttg', rs)
-    assert float(normwise(gg, g_orc).max()) <= 1e-10
+    assert (normwise(gg, g_orc) <= 1e-10 + 128 * EPS * boost_gamma(rs) ** 3).all()
 
 
 def test_gradient_not_built_for_ggttgg(mg):

@@ -17,6 +17,7 @@ import torch
 
 from oracle import me as orc
 from oracle import philox, rambo
+from rounding import EPS, boost_gamma
 
 pytestmark = pytest.mark.gpu
 
@@ -28,7 +29,6 @@ CONFIG = {  # process: (seed, events at full size)
 }
 # parity sizes the oracle evaluates in seconds: several 64-event pages + a ragged tail
 SMALL = {'eemumu': 4096 + 17, 'ggtt': 2048 + 33, 'ggttg': 640 + 5, 'ggttgg': 192 + 7}
-EPS = 2.0 ** -52
 
 
 def say(*a):
@@ -54,16 +54,6 @@ def engine(mg, proc, prec='fp64'):
         say('create', proc, prec)
         _ENG[key] = mg.MEEngine(proc, prec)
     return _ENG[key]
-
-
-def boost_gamma(r):
-    q0 = -torch.log(r[:, 2::4] * r[:, 3::4])
-    c = 2 * r[:, 0::4] - 1
-    ph = 2 * math.pi * r[:, 1::4]
-    st = torch.sqrt(1 - c * c)
-    q = torch.stack([q0, q0 * st * torch.cos(ph), q0 * st * torch.sin(ph), q0 * c], -1)
-    Q = q.sum(1)
-    return Q[:, 0] / torch.sqrt(Q[:, 0] ** 2 - (Q[:, 1:] ** 2).sum(-1))
 
 
 def rel(a, b):
@@ -244,3 +234,21 @@ def test_edge_cases_and_errors(mg):
         r, p_orc, _ = orc.sample('ggtt', 9, 0, n)
         got = e.sigmakin(e.events_mom(p_orc), n).cpu()
         assert float(rel(got, orc.matrix_element('ggtt', p_orc)).max()) <= 1e-12
+
+
+def test_module_shortcuts(mg):
+    """mg.sample / mg.sigmakin (cached default engines) give the engine's results."""
+    n = 100
+    rnd, mom, wgt = mg.sample(3, n, process='ggttgg')
+    me, evtw = mg.sigmakin(mom, n, wgt=wgt, process='ggttgg')
+    e = engine(mg, 'ggttgg')
+    r = e.rnd_events(rnd, n).cpu()
+    _, mom2, wgt2 = e.sample(3, n)
+    # AoSoA slots past nevt are not written: compare the events only
+    assert torch.equal(e.mom_events(mom, n), e.mom_events(mom2, n)) and torch.equal(wgt, wgt2)
+    assert torch.equal(me, e.sigmakin(mom2, n))
+    assert torch.equal(evtw, me * wgt)
+    p = e.mom_events(mom, 8).cpu()
+    ref = orc.matrix_element('ggttgg', p)
+    assert float(rel(me[:8].cpu(), ref).max()) <= 1e-12
+    assert torch.equal(r, orc.sample('ggttgg', 3, 0, n)[0])
