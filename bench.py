@@ -24,6 +24,42 @@ PEAK_FP64_VALU = 78.6e12       # FLOP/s, MI355X vector FP64 (256 CU x 4 SIMD x 1
 PEAK_FP32_VALU_UNPACKED = 78.6e12  # FLOP/s without packed-FP32 instructions (not used here)
 
 
+# ----------------------------------------------------------------------------- HBM traffic
+def kernel_source_hash(proc):
+    """sha256 over everything that defines the SIGMAKIN kernels of proc: the
+    shared headers, the process's kernel sources, its generated code and the
+    compiler flags.  HBM counters recorded under profiles/ are reported only
+    while this hash matches the one they were taken with."""
+    import hashlib
+    sys.path.insert(0, os.path.join(ROOT, 'paper_2106_12631_amd'))
+    from paper_2106_12631_amd import build as _build
+    csrc = os.path.join(ROOT, 'paper_2106_12631_amd', 'csrc')
+    names = sorted(n for n in os.listdir(csrc)
+                   if n.endswith('.h') or (n.startswith(f'sigmakin_{proc}_') and n.endswith('.hip')))
+    h = hashlib.sha256()
+    for n in names + [os.path.join('generated', f'{proc}.inc')]:
+        h.update(n.encode())
+        with open(os.path.join(csrc, n), 'rb') as fh:
+            h.update(fh.read())
+    h.update(' '.join(a for a in _build.FLAGS if not a.startswith('/')).encode())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(proc, nevt):
+    """{precision: HBM bytes per SIGMAKIN launch} from the ```traffic blocks
+    of profiles/*.md whose source hash and event count match, else {}."""
+    import glob
+    import re
+    want = kernel_source_hash(proc)
+    for path in sorted(glob.glob(os.path.join(ROOT, 'profiles', '*.md'))):
+        for blk in re.findall(r"```traffic\n(.*?)```", open(path).read(), re.S):
+            rec = json.loads(blk)
+            if rec.get('process') == proc and rec.get('nevt') == nevt and \
+                    rec.get('source_hash') == want:
+                return {k: v['hbm_bytes_per_launch'] for k, v in rec['kernels'].items()}
+    return {}
+
+
 # ----------------------------------------------------------------------------- CPU baseline
 def _oracle_chunk(task):
     proc, seed, start, count = task
@@ -52,34 +88,81 @@ def cpu_baseline(proc, seed, per_worker, workers):
 
 
 # ----------------------------------------------------------------------------- GPU
+def _median(x):
+    x = sorted(x)
+    n = len(x)
+    return 0.5 * (x[(n - 1) // 2] + x[n // 2])
+
+
 def run_gpu(mg, torch, proc, prec, seed, nevt, steps, warmup):
+    """Warm-up, then `steps` timed steps (sampler + SIGMAKIN) between two
+    device synchronisations; HIP events on the launching stream split each
+    step into its kernels.  Afterwards the same number of steps with the
+    matrix elements copied to pinned host memory gives the paper's third
+    timing scope (compute + device-to-host)."""
     eng = mg.MEEngine(proc, prec)
     dev = eng.device
     mom = eng.empty_mom(nevt)
     wgt = torch.empty(nevt, dtype=torch.float64, device=dev)
     me = torch.empty(nevt, dtype=torch.float64, device=dev)
-
-    def step():
-        eng.sample(seed, nevt, mom=mom, wgt=wgt)
-        eng.sigmakin(mom, nevt, me=me)
+    host = torch.empty(nevt, dtype=torch.float64, pin_memory=True)
 
     for _ in range(warmup):
-        step()
+        eng.sample(seed, nevt, mom=mom, wgt=wgt)
+        eng.sigmakin(mom, nevt, me=me)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps)]
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+    evs = [(ev(), ev(), ev()) for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
-        eng.sample(seed, nevt, mom=mom, wgt=wgt)
         evs[k][0].record(stream)
-        eng.sigmakin(mom, nevt, me=me)
+        eng.sample(seed, nevt, mom=mom, wgt=wgt)
         evs[k][1].record(stream)
+        eng.sigmakin(mom, nevt, me=me)
+        evs[k][2].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    k_ms = [a.elapsed_time(b) for a, b in evs]
+    k_ms = [b.elapsed_time(c) for a, b, c in evs]
+    step_ms = [a.elapsed_time(c) for a, b, c in evs]
     nonfinite = eng.count_nonfinite(me)
-    return eng, wall, k_ms, nonfinite
+    evd = [(ev(), ev()) for _ in range(steps)]
+    for k in range(steps):
+        evd[k][0].record(stream)
+        eng.sample(seed, nevt, mom=mom, wgt=wgt)
+        eng.sigmakin(mom, nevt, me=me)
+        host.copy_(me, non_blocking=True)
+        evd[k][1].record(stream)
+    torch.cuda.synchronize()
+    d2h_ms = [a.elapsed_time(b) for a, b in evd]
+    scopes = {
+        "sigmakin": nevt / (_median(k_ms) / 1e3),
+        "sample_sigmakin": nevt / (_median(step_ms) / 1e3),
+        "sample_sigmakin_dtoh": nevt / (_median(d2h_ms) / 1e3),
+        "unit": "MEs/s (median over the timed steps)",
+    }
+    return eng, wall, k_ms, nonfinite, scopes
+
+
+PEAK_MFMA = {'bf16': 2.5e15, 'f32': 157.3e12}  # dense FLOP/s, MI355X
+
+
+def mfma_work(ncol, nhel, prec, proc, seconds, nevt):
+    """Matrix-core work of the colour sum as executed: per helicity and wave
+    of 64 events, 2 parts x K blocks x 2 tiles of 32x32 outputs."""
+    bf16 = prec == 'mixed' and proc == 'ggttgg'
+    if bf16:
+        kb, k = (3 * ((ncol + 7) // 8) + 1) // 2, 16
+    else:
+        kb, k = (ncol + 1) // 2, 2
+    flops_evt = 2 * kb * 2 * (32 * 32 * k * 2) / 64 * nhel
+    achieved = flops_evt * nevt / seconds
+    peak = PEAK_MFMA['bf16' if bf16 else 'f32']
+    return {"dtype": "bf16" if bf16 else "f32", "flops_per_event": flops_evt,
+            "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak}
 
 
 def run_gradient(mg, torch, prec, nevt, steps, warmup, seed=4):
@@ -120,8 +203,8 @@ def run_gradient(mg, torch, prec, nevt, steps, warmup, seed=4):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
-    ap.add_argument('--steps', type=int, default=5)
-    ap.add_argument('--warmup', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=12)
+    ap.add_argument('--warmup', type=int, default=2)
     ap.add_argument('--process', default='ggttgg')
     ap.add_argument('--nevt', type=int, default=1 << 19)
     ap.add_argument('--seed', type=int, default=3)
@@ -157,10 +240,11 @@ def main():
     import paper_2106_12631_amd as mg
     meta = json.load(open(os.path.join(ROOT, 'paper_2106_12631_amd', 'csrc', 'generated',
                                        'meta.json')))[args.process]
+    traffic = recorded_traffic(args.process, args.nevt)
     results = {}
     for prec in args.precisions.split(','):
-        eng, wall, k_ms, nonfinite = run_gpu(mg, torch, args.process, prec, args.seed, args.nevt,
-                                             args.steps, args.warmup)
+        eng, wall, k_ms, nonfinite, scopes = run_gpu(mg, torch, args.process, prec, args.seed,
+                                                     args.nevt, args.steps, args.warmup)
         nhel = eng.layout.nhel_good
         flops_evt = (meta['flops_amp_per_hel'] + meta['flops_colour_per_hel']) * nhel
         k_avg = sum(k_ms) / len(k_ms) / 1e3
@@ -171,11 +255,15 @@ def main():
             "sigmakin_ms": k_avg * 1e3,
             "sigmakin_MEs_per_s": args.nevt / k_avg,
             "nonfinite": nonfinite,
+            "scopes": scopes,
             "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                          "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
-                         "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                         "frac": achieved / PEAK_FP64_VALU, "traffic": traffic.get(prec),
                          "flops_per_event": flops_evt},
         }
+        if prec.startswith('mixed'):
+            results[prec]["mfma"] = mfma_work(meta['ncol'], nhel, prec, args.process, k_avg,
+                                              args.nevt)
     gradient = None
     if not args.no_gradient:
         gradient = {"workload": "ggttg 262144 events seed 4: d(w |M|^2)/dr, d log w/dr "

@@ -158,6 +158,37 @@ int mg_sigmakin_hel(const mg_handle_t* h, const double* mom, int64_t nevt, doubl
 int mg_adjoint(const mg_handle_t* h, const double* rnd, int64_t nevt, const double* gbar_or_null,
                double* grad_rnd, double* grad_logw_or_null, double* f_or_null, void* stream);
 
+/* Cross-section statistics of n weighted events f = w |M|^2 (device FP64,
+ * e.g. evtw from mg_sigmakin): stats[0] = sum of the finite f, stats[1] =
+ * sum of their squares, stats[2] = their maximum (0 if none), stats[3] =
+ * how many are finite; stats is a device array of 4 doubles.  One block of
+ * 1024 threads in a fixed summation order, so the result does not depend on
+ * timing (Sec. II: cross section from weighted events). */
+int mg_xsec_stats(const double* f, int64_t n, double* stats, void* stream);
+
+/* Host: cross section and Monte Carlo error in pb from stats copied to the
+ * host, for n events of h's process:
+ *   sigma = (hbar c)^2 (2 pi)^(4 - 3 nfinal) / (2 s) * stats[0] / n
+ * (massless partons at fixed sqrt(s); RAMBO weights without 2 pi factors),
+ *   error = same factor * sqrt((stats[1]/n - (stats[0]/n)^2) / (n - 1)).
+ * Non-finite events count as zero.  MG_EINVAL for n < 2 or null pointers. */
+int mg_xsec(const mg_handle_t* h, const double* stats_host, int64_t n, double* sigma_pb,
+            double* error_pb);
+
+/* Bytes of device workspace mg_unweight needs for n events (8-byte
+ * aligned; contents need not be initialised). */
+int64_t mg_unweight_workspace_bytes(int64_t n);
+
+/* Hit-or-miss unweighting (Sec. II: unweighted events from weighted ones):
+ * event i is kept iff u_i * fmax < f[i], u_i the Philox uniform of (seed,
+ * global event evt_offset + i) at counter block 2^31 (no sampler uses that
+ * block, so the sampling seed may be reused).  The kept indices i (0-based,
+ * increasing) go to idx_out[0 .. *count_out) (device; idx_out must hold n
+ * entries), *count_out is a device int64.  NaN f is never kept.  Three
+ * kernels (count, scan, write) on `stream`. */
+int mg_unweight(const double* f, int64_t n, double fmax, uint64_t seed, int64_t evt_offset,
+                int64_t* idx_out, int64_t* count_out, void* workspace, void* stream);
+
 /* Number of non-finite entries of x[0..n) accumulated into *d_count (a
  * device int64 the caller zeroes first). */
 int mg_count_nonfinite(const double* x, int64_t n, int64_t* d_count, void* stream);

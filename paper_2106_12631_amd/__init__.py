@@ -12,7 +12,7 @@ import os
 import torch
 
 __all__ = ['MEEngine', 'MEWeight', 'PROCESSES', 'PRECISIONS', 'lib', 'library_path', 'engine',
-           'sample', 'sigmakin']
+           'sample', 'sigmakin', 'xsec_stats', 'unweight']
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 PROCESSES = {'eemumu': 0, 'ggtt': 1, 'ggttg': 2, 'ggttgg': 3}
@@ -64,11 +64,16 @@ def lib():
         'mg_sigmakin_hel': [vp, vp, i64, vp, vp],
         'mg_count_nonfinite': [vp, i64, vp, vp],
         'mg_adjoint': [vp, vp, i64, vp, vp, vp, vp, vp],
+        'mg_xsec_stats': [vp, i64, vp, vp],
+        'mg_xsec': [vp, vp, i64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+        'mg_unweight': [vp, i64, ctypes.c_double, u64, i64, vp, vp, vp, vp],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = ci
+    L.mg_unweight_workspace_bytes.argtypes = [i64]
+    L.mg_unweight_workspace_bytes.restype = i64
     L.mg_strerror.argtypes = [ci]
     L.mg_strerror.restype = ctypes.c_char_p
     _LIB = L
@@ -215,6 +220,17 @@ class MEEngine:
         r of shape (nevt, nrnd) (see MEWeight)."""
         return MEWeight.apply(r, self)
 
+    def cross_section(self, evtw, nevt):
+        """(sigma [pb], Monte Carlo error [pb], stats) from the weighted
+        events evtw = w |M|^2 (mg_xsec_stats on the device, mg_xsec on the
+        host; stats = sum, sum of squares, max, finite count)."""
+        st = xsec_stats(evtw[:nevt])
+        host = st.cpu()
+        sig, err = ctypes.c_double(), ctypes.c_double()
+        _check(lib().mg_xsec(self._h, ctypes.c_void_p(host.data_ptr()), nevt, ctypes.byref(sig),
+                             ctypes.byref(err)), 'mg_xsec')
+        return sig.value, err.value, host
+
     def count_nonfinite(self, x):
         cnt = torch.zeros(1, dtype=torch.int64, device=self.device)
         _check(lib().mg_count_nonfinite(_ptr(x), x.numel(), _ptr(cnt), _stream(self.device)),
@@ -272,3 +288,25 @@ def sample(seed, nevt, process='ggttgg', offset=0, keep_rnd=True):
 def sigmakin(mom, nevt, wgt=None, process='ggttgg', precision='fp64'):
     """|M|^2 per event for AoSoA momenta (and w |M|^2 if wgt is given)."""
     return engine(process, precision).sigmakin(mom, nevt, wgt=wgt)
+
+
+def xsec_stats(f):
+    """Device tensor (4,) = (sum, sum of squares, max, count) of the finite f."""
+    f = f.contiguous()
+    out = torch.empty(4, dtype=torch.float64, device=f.device)
+    _check(lib().mg_xsec_stats(_ptr(f), f.numel(), _ptr(out), _stream(f.device)), 'mg_xsec_stats')
+    return out
+
+
+def unweight(f, fmax, seed, evt_offset=0):
+    """Hit-or-miss unweighting: device int64 tensor of the kept event indices
+    (increasing): event i is kept iff u_i fmax < f[i] (mg_unweight)."""
+    f = f.contiguous()
+    n = f.numel()
+    idx = torch.empty(max(n, 1), dtype=torch.int64, device=f.device)
+    cnt = torch.zeros(1, dtype=torch.int64, device=f.device)
+    nb = lib().mg_unweight_workspace_bytes(n)
+    ws = torch.empty((nb + 7) // 8, dtype=torch.int64, device=f.device)
+    _check(lib().mg_unweight(_ptr(f), n, float(fmax), int(seed), int(evt_offset), _ptr(idx),
+                             _ptr(cnt), _ptr(ws), _stream(f.device)), 'mg_unweight')
+    return idx[:int(cnt.item())]

@@ -360,6 +360,45 @@ int mg_count_nonfinite(const double* x, int64_t n, int64_t* d_count, void* strea
   return hip_status();
 }
 
+int mg_xsec_stats(const double* f, int64_t n, double* stats, void* stream) {
+  if (n < 0 || !stats || (n > 0 && !f)) return MG_EINVAL;
+  if (!aligned8(f) || !aligned8(stats)) return MG_EALIGN;
+  launch_xsec_stats(f, n, stats, (hipStream_t)stream);
+  return hip_status();
+}
+
+int mg_xsec(const mg_handle_t* h, const double* st, int64_t n, double* sigma_pb,
+            double* error_pb) {
+  if (!h || !st || !sigma_pb || !error_pb || n < 2) return MG_EINVAL;
+  const int nfinal = PROC_INFO[h->proc].npar - 2;
+  const double s = h->prm.sqrts * h->prm.sqrts;
+  const double hbarc2_pb = 0.3893793721e9;
+  const double scale = hbarc2_pb * pow(2.0 * M_PI, 4 - 3 * nfinal) / (2.0 * s);
+  const double mean = st[0] / (double)n;
+  double var = st[1] / (double)n - mean * mean;
+  if (var < 0.0) var = 0.0;
+  *sigma_pb = scale * mean;
+  *error_pb = scale * sqrt(var / (double)(n - 1));
+  return MG_OK;
+}
+
+int64_t mg_unweight_workspace_bytes(int64_t n) {
+  return n <= 0 ? 8 : unweight_blocks(n) * (int64_t)sizeof(int64_t);
+}
+
+int mg_unweight(const double* f, int64_t n, double fmax, uint64_t seed, int64_t evt_offset,
+                int64_t* idx_out, int64_t* count_out, void* workspace, void* stream) {
+  if (n < 0 || evt_offset < 0 || !count_out || (n > 0 && (!f || !idx_out || !workspace)) ||
+      !(fmax >= 0.0))
+    return MG_EINVAL;
+  if (!aligned8(f) || !aligned8(idx_out) || !aligned8(count_out) || !aligned8(workspace))
+    return MG_EALIGN;
+  if (launch_unweight(f, n, fmax, seed, evt_offset, idx_out, count_out, (int64_t*)workspace,
+                      (hipStream_t)stream))
+    return MG_EINVAL;
+  return hip_status();
+}
+
 const char* mg_strerror(int code) {
   switch (code) {
     case MG_OK: return "success";

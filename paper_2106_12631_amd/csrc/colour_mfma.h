@@ -4,27 +4,37 @@
 //   |M|^2 = sum_ij C_ij Re(conj(J_i) J_j) = Re^T C Re + Im^T C Im
 // with the event-independent colour matrix C (Sec. II).  For a wave of 64
 // events this is a dense product Z = C [Re | Im] of an ncol x ncol matrix
-// with an ncol x 128 matrix (64 events x real/imaginary part), followed by
-// the per-event dot products sum_i J_i Z_i.  The jamps come out of the
-// amplitude code one event per lane; they are staged through LDS into the
-// operand layout of the MFMA instructions:
+// with an ncol x 128 matrix, followed by the per-event dot products
+// sum_i J_i Z_i.  The product runs as two 32-event tiles per part (events
+// 0-31: "lo", 32-63: "hi"), in the operand layouts
 //
 //   32x32 output, register r of lane l holds D[m][n] with n = l % 32,
 //   m = 8 (r / 4) + 4 (l / 32) + r % 4;
 //   v_mfma_f32_32x32x2_f32:  A[m = l%32][k = l/32],         B[k = l/32][n = l%32]
 //   v_mfma_f32_32x32x16_bf16: A[m = l%32][k = 8(l/32) + j],  B[k = 8(l/32) + j][n = l%32]
 //
+// The amplitudes come out of the generated code one event per lane.  Lane l
+// and lane l + 32 hold the two halves of every B column and D row group the
+// tiles need, so one v_permlane32_swap per register builds both tiles'
+// operands from the lane's own values: with a from every lane and b from
+// every lane, swap(a, b) returns r0 = (a of lanes 0-31, b of lanes 0-31
+// moved up) -- the lo tile -- and r1 = (a of lanes 32-63 moved down, b of
+// lanes 32-63) -- the hi tile.  No LDS and no barrier is involved.
+//
 // Two forms:
 //   ColourMfmaF32   FP32 operands (C integer numerators exact in FP32),
 //                   FP32 accumulation;
-//   ColourMfmaBf16  the jamps split into three BF16 terms hi + mid + lo
-//                   (together the 24 significand bits of FP32) against the
-//                   integer numerators of C, exact in BF16 (|C| <= 512 with
-//                   at most 8 significant bits), FP32 accumulation.  The
-//                   three splits are laid side by side along K, so one
-//                   product [C C C] [hi; mid; lo] gives C J.
-// Every lane of the wave must call sum() together (it uses LDS exchange and
-// block barriers); the kernels using it run one wave per block.
+//   ColourMfmaBf16  each FP32 jamp split exactly into three BF16 terms by
+//                   truncation (hi = top 8 significand bits, mid = next 8,
+//                   lo = the rest, exact because it has at most 8 bits)
+//                   against the integer numerators of C, exact in BF16
+//                   (|C| <= 512 with at most 8 significant bits), FP32
+//                   accumulation.  K runs over (split, colour group of 8):
+//                   chunk c = s G + g holds split s of colours 8g .. 8g+7,
+//                   and C is repeated for the three splits, so one product
+//                   gives C (hi + mid + lo) = C J.
+// Every lane of the wave must call sum() together (cross-lane operations);
+// the kernels using it run one wave per block.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -34,35 +44,56 @@ namespace mg {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short ushort8 __attribute__((ext_vector_type(8)));
+typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
 
-// round-to-nearest-even FP32 -> BF16 bits (inputs are finite)
-__device__ __forceinline__ unsigned short bf16_bits(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ float bf16_value(unsigned short b) {
-  return __uint_as_float((unsigned)b << 16);
+// exact FP32 -> BF16 bits for values with at most 8 significant bits
+__device__ __forceinline__ unsigned short bf16_exact_bits(float x) {
+  return (unsigned short)(__float_as_uint(x) >> 16);
 }
 
-// dot of the 32x32 block D with the staged jamps in D's layout, reduced over
-// the two half-waves: every lane ends with the value of its column
+// (lo tile, hi tile) operands from this lane's a and b (see above)
+__device__ __forceinline__ void swap_halves(unsigned a, unsigned b, unsigned& lo, unsigned& hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+  lo = r[0];
+  hi = r[1];
+}
+__device__ __forceinline__ void swap_halves(float a, float b, float& lo, float& hi) {
+  unsigned ul, uh;
+  swap_halves(__float_as_uint(a), __float_as_uint(b), ul, uh);
+  lo = __uint_as_float(ul);
+  hi = __uint_as_float(uh);
+}
+
+// Dot of the two tiles' 32x32 outputs with the amplitudes x (this lane's
+// event, one part) in D's row layout, summed into this lane's event.
+// part_lo / part_hi accumulate over the real and imaginary parts.
 template <int NCOL>
-__device__ __forceinline__ float block_dot(const floatx16& d, const float* f, int lane) {
-  float s = 0.f;
+__device__ __forceinline__ void tile_dots(const floatx16& dlo, const floatx16& dhi,
+                                          const float (&x)[NCOL], float& part_lo,
+                                          float& part_hi) {
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    if (m < NCOL) s += d[r] * f[m * 64];
+    const int mlo = 8 * (r / 4) + r % 4, mhi = mlo + 4;
+    if (mlo < NCOL) {
+      float jlo, jhi;
+      swap_halves(x[mlo], mhi < NCOL ? x[mhi] : 0.f, jlo, jhi);
+      part_lo += dlo[r] * jlo;
+      part_hi += dhi[r] * jhi;
+    }
   }
-  return s + __shfl_xor(s, 32);
+}
+
+// lane l < 32: its event's total is part_lo(l) + part_lo(l + 32);
+// lane l >= 32: part_hi(l - 32) + part_hi(l)
+__device__ __forceinline__ float combine_halves(float part_lo, float part_hi, int lane) {
+  float from_hi, from_lo;  // r0 of lanes >= 32 = part_hi of lane - 32; r1 of lanes < 32 = part_lo of lane + 32
+  swap_halves(part_lo, part_hi, from_hi, from_lo);
+  return lane < 32 ? part_lo + from_lo : part_hi + from_hi;
 }
 
 template <int NCOL>
 struct ColourMfmaF32 {
-  static constexpr int KB = (NCOL + 1) / 2;   // K blocks of 2
-  static constexpr int LDS_BYTES = 2 * NCOL * 64 * 4;
+  static constexpr int KB = (NCOL + 1) / 2;  // K blocks of 2
   float a[KB];
 
   // cnum: the NCOL x NCOL integer numerators of C, row-major
@@ -76,97 +107,103 @@ struct ColourMfmaF32 {
   }
 
   // returns sum_ij C_ij Re(conj(J_i) J_j) (numerators of C) for this lane's event
-  __device__ __forceinline__ float sum(void* lds_raw, const cx<float> (&J)[NCOL], int lane) {
-    float* f = (float*)lds_raw;  // [part][k][64]
+  __device__ __forceinline__ float sum(const cx<float> (&J)[NCOL], int lane) {
+    float part_lo = 0.f, part_hi = 0.f;
 #pragma unroll
-    for (int k = 0; k < NCOL; ++k) {
-      f[k * 64 + lane] = J[k].r;
-      f[(NCOL + k) * 64 + lane] = J[k].i;
-    }
-    __syncthreads();
-    float tot = 0.f;
+    for (int part = 0; part < 2; ++part) {
+      float x[NCOL];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int part = b >> 1, half = b & 1;
-      const float* col = f + part * NCOL * 64 + half * 32 + (lane & 31);
-      floatx16 d = {0};
+      for (int k = 0; k < NCOL; ++k) x[k] = part ? J[k].i : J[k].r;
+      floatx16 dlo = {0}, dhi = {0};
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        const int k = 2 * kb + (lane >> 5);
-        const float bv = (k < NCOL) ? col[k * 64] : 0.f;
-        d = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb], bv, d, 0, 0, 0);
+        float blo, bhi;
+        swap_halves(x[2 * kb], 2 * kb + 1 < NCOL ? x[2 * kb + 1] : 0.f, blo, bhi);
+        dlo = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb], blo, dlo, 0, 0, 0);
+        dhi = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb], bhi, dhi, 0, 0, 0);
       }
-      const float s = block_dot<NCOL>(d, col, lane);
-      if (half == (lane >> 5)) tot += s;
+      tile_dots<NCOL>(dlo, dhi, x, part_lo, part_hi);
     }
-    __syncthreads();
-    return tot;
+    return combine_halves(part_lo, part_hi, lane);
   }
 };
 
 template <int NCOL>
 struct ColourMfmaBf16 {
-  static constexpr int KP = 3 * NCOL;           // hi, mid, lo side by side along K
-  static constexpr int KB = (KP + 15) / 16;     // K blocks of 16
-  static constexpr int KPAD = KB * 16;
-  static constexpr int LDS_F32 = 2 * NCOL * 64 * 4;
-  static constexpr int LDS_BYTES = LDS_F32 + 128 * KPAD * 2;
+  static constexpr int G = (NCOL + 7) / 8;  // colour groups of 8
+  static constexpr int NCH = 3 * G;         // chunks (split, group) of 8 K entries
+  static constexpr int KB = (NCH + 1) / 2;  // K blocks of 16 (two chunks)
   bf16x8 a[KB];
 
   __device__ __forceinline__ void init(const int* cnum, int lane) {
     const int m = lane & 31, kh = lane >> 5;
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-      ushort8 u;
+      const int c = 2 * kb + kh, g = c % G;
+      unsigned u[4];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int kk = 16 * kb + 8 * kh + j;
-        u[j] = (m < NCOL && kk < KP) ? bf16_bits((float)cnum[m * NCOL + kk % NCOL])
-                                     : (unsigned short)0;
+      for (int q = 0; q < 4; ++q) {
+        unsigned short h[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int col = 8 * g + 2 * q + t;
+          h[t] = (m < NCOL && c < NCH && col < NCOL)
+                     ? bf16_exact_bits((float)cnum[m * NCOL + col])
+                     : (unsigned short)0;
+        }
+        u[q] = (unsigned)h[0] | ((unsigned)h[1] << 16);
       }
-      a[kb] = __builtin_bit_cast(bf16x8, u);
+      const uintx4 v = {u[0], u[1], u[2], u[3]};
+      a[kb] = __builtin_bit_cast(bf16x8, v);
     }
   }
 
-  __device__ __forceinline__ float sum(void* lds_raw, const cx<float> (&J)[NCOL], int lane) {
-    float* f = (float*)lds_raw;                                       // [part][k][64]
-    unsigned short* h = (unsigned short*)((char*)lds_raw + LDS_F32);  // [column][KPAD]
+  __device__ __forceinline__ float sum(const cx<float> (&J)[NCOL], int lane) {
+    float part_lo = 0.f, part_hi = 0.f;
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
-      unsigned short* row = h + (part * 64 + lane) * KPAD;
+      float x[NCOL];
 #pragma unroll
-      for (int k = 0; k < NCOL; ++k) {
-        const float x = part ? J[k].i : J[k].r;
-        f[(part * NCOL + k) * 64 + lane] = x;
-        const unsigned short b0 = bf16_bits(x);
-        const float r1 = x - bf16_value(b0);
-        const unsigned short b1 = bf16_bits(r1);
-        const float r2 = r1 - bf16_value(b1);
-        row[k] = b0;
-        row[NCOL + k] = b1;
-        row[2 * NCOL + k] = bf16_bits(r2);
+      for (int k = 0; k < NCOL; ++k) x[k] = part ? J[k].i : J[k].r;
+      // exact three-term split by truncation; each term's bits in the upper
+      // half of a 32-bit word
+      unsigned sp[3][8 * G];
+#pragma unroll
+      for (int k = 0; k < 8 * G; ++k) {
+        const float v = k < NCOL ? x[k] : 0.f;
+        const unsigned hi = __float_as_uint(v) & 0xFFFF0000u;
+        const float r1 = v - __uint_as_float(hi);
+        const unsigned mid = __float_as_uint(r1) & 0xFFFF0000u;
+        const float r2 = r1 - __uint_as_float(mid);
+        sp[0][k] = hi;
+        sp[1][k] = mid;
+        sp[2][k] = __float_as_uint(r2);
       }
-#pragma unroll
-      for (int k = KP; k < KPAD; ++k) row[k] = 0;
-    }
-    __syncthreads();
-    float tot = 0.f;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int part = b >> 1, half = b & 1;
-      const int column = part * 64 + half * 32 + (lane & 31);
-      const ushort8* src = (const ushort8*)(h + column * KPAD + 8 * (lane >> 5));
-      floatx16 d = {0};
+      floatx16 dlo = {0}, dhi = {0};
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        const bf16x8 bv = __builtin_bit_cast(bf16x8, src[2 * kb]);
-        d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kb], bv, d, 0, 0, 0);
+        unsigned ulo[4], uhi[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          unsigned w[2];
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const int c = 2 * kb + t, s = c / G, g = c % G;
+            w[t] = c < NCH ? (sp[s][8 * g + 2 * q] >> 16) | (sp[s][8 * g + 2 * q + 1] & 0xFFFF0000u)
+                           : 0u;
+          }
+          swap_halves(w[0], w[1], ulo[q], uhi[q]);
+        }
+        const uintx4 vlo = {ulo[0], ulo[1], ulo[2], ulo[3]};
+        const uintx4 vhi = {uhi[0], uhi[1], uhi[2], uhi[3]};
+        dlo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kb], __builtin_bit_cast(bf16x8, vlo), dlo,
+                                                      0, 0, 0);
+        dhi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kb], __builtin_bit_cast(bf16x8, vhi), dhi,
+                                                      0, 0, 0);
       }
-      const float s = block_dot<NCOL>(d, f + part * NCOL * 64 + half * 32 + (lane & 31), lane);
-      if (half == (lane >> 5)) tot += s;
+      tile_dots<NCOL>(dlo, dhi, x, part_lo, part_hi);
     }
-    __syncthreads();
-    return tot;
+    return combine_halves(part_lo, part_hi, lane);
   }
 };
 

@@ -179,12 +179,19 @@ __device__ __forceinline__ void opaque4(cx<T> (&w)[4]) {
 // of another group and kept live in between) and the machine scheduler may
 // not move instructions across the fence.  The generated code orders its
 // work to bound the number of live wavefunctions; the fence keeps that order.
-template <int N, typename R>
+// With UNI the momenta are the same in every lane of the wave (one event per
+// wave) and stay in scalar registers.
+__device__ __forceinline__ void opaque_uniform(double& x) { asm volatile("" : "+s"(x)); }
+
+template <bool UNI = false, int N, typename R>
 __device__ __forceinline__ void fence(R (&p)[N][4]) {
 #pragma unroll
   for (int k = 0; k < N; ++k)
 #pragma unroll
-    for (int m = 0; m < 4; ++m) opaque(p[k][m]);
+    for (int m = 0; m < 4; ++m) {
+      if constexpr (UNI) opaque_uniform(p[k][m]);
+      else opaque(p[k][m]);
+    }
   __builtin_amdgcn_sched_barrier(0);
 }
 

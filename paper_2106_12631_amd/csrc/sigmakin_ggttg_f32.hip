@@ -10,10 +10,10 @@ struct P_ggttg {
   static constexpr int NCOL = gen_ggttg::NCOL;
   static constexpr int CDEN = gen_ggttg::CDEN;
   __device__ static __forceinline__ const int* cnum() { return &gen_ggttg::CNUM[0][0]; }
-  template <typename T>
+  template <typename T, bool UNI = false>
   __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<T>& c, cx<T> (&J)[NCOL]) {
-    gen_ggttg::jamps<T>(p, h, c, J);
+    gen_ggttg::jamps<T, UNI>(p, h, c, J);
   }
   template <typename T>
   __device__ static __forceinline__ T colour_sum(const cx<T> (&J)[NCOL]) {

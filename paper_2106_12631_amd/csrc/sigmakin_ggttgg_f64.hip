@@ -10,10 +10,10 @@ struct P_ggttgg {
   static constexpr int NCOL = gen_ggttgg::NCOL;
   static constexpr int CDEN = gen_ggttgg::CDEN;
   __device__ static __forceinline__ const int* cnum() { return &gen_ggttgg::CNUM[0][0]; }
-  template <typename T>
+  template <typename T, bool UNI = false>
   __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<T>& c, cx<T> (&J)[NCOL]) {
-    gen_ggttgg::jamps<T>(p, h, c, J);
+    gen_ggttgg::jamps<T, UNI>(p, h, c, J);
   }
   template <typename T>
   __device__ static __forceinline__ T colour_sum(const cx<T> (&J)[NCOL]) {
@@ -23,7 +23,11 @@ struct P_ggttgg {
 
 int launch_sigmakin_ggttgg_f64(const MeArgs& a, const double* mom, int64_t nevt, double* me,
                               const double* wgt, double* evtw, double* mehel, hipStream_t s) {
+#ifdef MG_EVENT_PER_LANE_F64
   return sigmakin_launch<P_ggttgg, double, 64>(a, a.c64, mom, nevt, me, wgt, evtw, mehel, s);
+#else
+  return sigmakin_hpl_launch<P_ggttgg, double, 64>(a, a.c64, mom, nevt, me, wgt, evtw, mehel, s);
+#endif
 }
 
 }  // namespace mg

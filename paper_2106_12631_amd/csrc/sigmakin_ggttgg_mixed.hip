@@ -10,10 +10,10 @@ struct P_ggttgg {
   static constexpr int NCOL = gen_ggttgg::NCOL;
   static constexpr int CDEN = gen_ggttgg::CDEN;
   __device__ static __forceinline__ const int* cnum() { return &gen_ggttgg::CNUM[0][0]; }
-  template <typename T>
+  template <typename T, bool UNI = false>
   __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<float>& c, cx<float> (&J)[NCOL]) {
-    gen_ggttgg::jamps_f32m(p, h, c, J);
+    gen_ggttgg::jamps_f32m<UNI>(p, h, c, J);
   }
   template <typename T>
   __device__ static __forceinline__ T colour_sum(const cx<T> (&J)[NCOL]) {
@@ -23,12 +23,20 @@ struct P_ggttgg {
 
 int launch_sigmakin_ggttgg_mfma_f32(const MeArgs& a, const double* mom, int64_t nevt, double* me,
                                 const double* wgt, double* evtw, hipStream_t s) {
+#ifdef MG_HPL_MIXED
+  return sigmakin_mixed_hpl_launch<P_ggttgg, ColourMfmaF32>(a, mom, nevt, me, wgt, evtw, s);
+#else
   return sigmakin_mixed_launch<P_ggttgg, ColourMfmaF32>(a, mom, nevt, me, wgt, evtw, s);
+#endif
 }
 
 int launch_sigmakin_ggttgg_mfma_bf16(const MeArgs& a, const double* mom, int64_t nevt, double* me,
                                  const double* wgt, double* evtw, hipStream_t s) {
+#ifdef MG_HPL_MIXED
+  return sigmakin_mixed_hpl_launch<P_ggttgg, ColourMfmaBf16>(a, mom, nevt, me, wgt, evtw, s);
+#else
   return sigmakin_mixed_launch<P_ggttgg, ColourMfmaBf16>(a, mom, nevt, me, wgt, evtw, s);
+#endif
 }
 
 }  // namespace mg

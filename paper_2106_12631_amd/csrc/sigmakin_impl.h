@@ -59,7 +59,6 @@ __global__ void __launch_bounds__(64)
     sigmakin_mixed_kernel(const double* __restrict__ mom, int64_t nevt, double* __restrict__ me,
                           const double* __restrict__ wgt, double* __restrict__ evtw, HelList hl,
                           Couplings<float> c, double inv_iden) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[CS<P::NCOL>::LDS_BYTES];
   const int lane = threadIdx.x;
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   const bool valid = i < nevt;
@@ -76,7 +75,7 @@ __global__ void __launch_bounds__(64)
     load_event<P>(mom, iq, q);
     cx<float> J[P::NCOL];
     P::template jamps<float>(q, hl.code[k], c, J);
-    acc += (double)cs.sum(lds, J, lane);
+    acc += (double)cs.sum(J, lane);
   }
   if (valid) {
     const double m = acc * scale;
@@ -104,6 +103,87 @@ int sigmakin_launch(const MeArgs& a, const Couplings<T>& c, const double* mom, i
   }
   sigmakin_kernel<P, T, BS><<<g, BS, 0, s>>>(mom, nevt, me, wgt, evtw, mehel, hl, c, a.inv_iden);
   return 0;
+}
+
+// One event per wave, one helicity per lane: for a process with 64
+// helicities, all kept, lane h of block i computes helicity h of event i.
+// The momenta are the same in every lane and stay in scalar registers (the
+// generated code is instantiated with uniform momenta), which leaves the
+// vector registers to the wavefunctions and colour-flow amplitudes; the
+// helicity sum is a wave reduction.  The grid has exactly nevt blocks.
+template <class P, typename T>
+__global__ void __launch_bounds__(64)
+    sigmakin_hpl_kernel(const double* __restrict__ mom, int64_t nevt, double* __restrict__ me,
+                        const double* __restrict__ wgt, double* __restrict__ evtw,
+                        double* __restrict__ mehel, Couplings<T> c, double inv_iden) {
+  static_assert((1 << P::NPAR) == 64, "one helicity per lane of a wave64");
+  const int64_t i = blockIdx.x;
+  const unsigned h = threadIdx.x;
+  double q[P::NPAR][4];
+  load_event<P>(mom, i, q);
+  cx<T> J[P::NCOL];
+  P::template jamps<T, true>(q, h, c, J);
+  double v = (double)P::template colour_sum<T>(J);
+  if (mehel) mehel[(int64_t)h * nevt + i] = v;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (h == 0) {
+    const double m = v * inv_iden;
+    if (me) me[i] = m;
+    if (evtw) evtw[i] = m * wgt[i];
+  }
+}
+
+// helicity-per-lane launch when every helicity is kept, else the
+// event-per-lane kernel
+template <class P, typename T, int BS>
+int sigmakin_hpl_launch(const MeArgs& a, const Couplings<T>& c, const double* mom, int64_t nevt,
+                        double* me, const double* wgt, double* evtw, double* mehel,
+                        hipStream_t s) {
+  if ((mehel || a.hel.n == (1 << P::NPAR)) && nevt > 0 && nevt <= 0x7FFFFFFF) {
+    sigmakin_hpl_kernel<P, T><<<(unsigned)nevt, 64, 0, s>>>(mom, nevt, me, wgt, evtw, mehel, c,
+                                                           a.inv_iden);
+    return 0;
+  }
+  return sigmakin_launch<P, T, BS>(a, c, mom, nevt, me, wgt, evtw, mehel, s);
+}
+
+// Mixed precision, one event per wave and one helicity per lane: the 64
+// helicities' colour-flow amplitudes are the 64 columns of the MFMA colour
+// sum, whose per-lane results are then summed over the wave in FP64.
+template <class P, template <int> class CS>
+__global__ void __launch_bounds__(64)
+    sigmakin_mixed_hpl_kernel(const double* __restrict__ mom, int64_t nevt,
+                              double* __restrict__ me, const double* __restrict__ wgt,
+                              double* __restrict__ evtw, Couplings<float> c, double inv_iden) {
+  static_assert((1 << P::NPAR) == 64, "one helicity per lane of a wave64");
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  CS<P::NCOL> cs;
+  cs.init(P::cnum(), lane);
+  double q[P::NPAR][4];
+  load_event<P>(mom, i, q);
+  cx<float> J[P::NCOL];
+  P::template jamps<float, true>(q, (unsigned)lane, c, J);
+  double v = (double)cs.sum(J, lane);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (lane == 0) {
+    const double m = v * (inv_iden / P::CDEN);
+    if (me) me[i] = m;
+    if (evtw) evtw[i] = m * wgt[i];
+  }
+}
+
+template <class P, template <int> class CS>
+int sigmakin_mixed_hpl_launch(const MeArgs& a, const double* mom, int64_t nevt, double* me,
+                              const double* wgt, double* evtw, hipStream_t s) {
+  if (a.hel.n == (1 << P::NPAR) && nevt > 0 && nevt <= 0x7FFFFFFF) {
+    sigmakin_mixed_hpl_kernel<P, CS><<<(unsigned)nevt, 64, 0, s>>>(mom, nevt, me, wgt, evtw,
+                                                                  a.c32, a.inv_iden);
+    return 0;
+  }
+  return sigmakin_mixed_launch<P, CS>(a, mom, nevt, me, wgt, evtw, s);
 }
 
 }  // namespace mg

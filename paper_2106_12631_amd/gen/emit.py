@@ -418,7 +418,7 @@ def emit_body(pd, coefs, order, bils, need, budget, evict_ext=False):
         nd = need(k)
         pin = {n.idx for n in nd}
         if pos % FENCE_EVERY == 0:
-            L.append("  fence(p);")
+            L.append("  fence<UNI>(p);")
         names = [ensure(n, pos, pin) for n in nd]
         cl, cr = FFV[(d.fin.flav, d.vec.flav)]
         if len(nd) == 2:   # shared bilinear . vector
@@ -738,6 +738,7 @@ def generate(name):
         stats[prec] = dict(flops_amp_per_hel=algo, flops_executed_per_hel=execd,
                            peak_live_wavefunctions=peak, recomputed=rec)
         jparam = f"cx<{T}> (&J)[{ncol}]"
+        w("template <bool UNI = false>")
         w(f"__device__ __forceinline__ void jamps_{prec}({Rt} (&p)[{npar}][4], unsigned hcode,")
         w(f"                                          const Couplings<{Ct}>& c, {jparam}) {{")
         w(f"  using T = {T};")
@@ -747,10 +748,11 @@ def generate(name):
         L.extend(body)
         w("}")
         w("")
-    w("template <typename T>")
+    w("template <typename T, bool UNI = false>")
     w(f"__device__ __forceinline__ void jamps(double (&p)[{npar}][4], unsigned hcode,")
     w(f"                                      const Couplings<T>& c, cx<T> (&J)[{ncol}]) {{")
-    w("  if constexpr (sizeof(T) == 8) jamps_f64(p, hcode, c, J); else jamps_f32(p, hcode, c, J);")
+    w("  if constexpr (sizeof(T) == 8) jamps_f64<UNI>(p, hcode, c, J);")
+    w("  else jamps_f32<UNI>(p, hcode, c, J);")
     w("}")
     w("")
     # colour sum: sum_i J_i^* (sum_j C_ij J_j) using the symmetry of C
@@ -788,6 +790,7 @@ def generate(name):
             A.append(f"                                            double (&pb)[{npar}][4]) {{")
             A.append(f"  using T = {T};")
             A.append(f"  using R = double;")
+            A.append(f"  constexpr bool UNI = false;")
             A.append(f"  cx<T> J[{ncol}];")
             for k in range(ncol):
                 A.append(f"  J[{k}] = cx<T>{{(T)0, (T)0}};")

@@ -1,0 +1,65 @@
+"""The phase-space adaptation map and its training loop (CPU, torch).
+
+* the warp is the identity for zero logits, monotone, maps (0,1) into (0,1),
+  and its Jacobian equals the product of the finite-difference derivatives;
+* for a separable peaked integrand with a known integral, training reduces
+  the relative second moment by a large factor and the adapted estimate of
+  the integral stays within four standard errors of the exact value.
+"""
+import math
+
+import pytest
+import torch
+
+from paper_2106_12631_amd import adapt
+
+
+def test_identity_and_jacobian():
+    torch.manual_seed(0)
+    m = adapt.WarpMap(3, 8)
+    u = torch.rand(100, 3, dtype=torch.float64)
+    x, jac = m(u)
+    assert torch.allclose(x, u, rtol=0, atol=1e-15) and torch.allclose(jac, torch.ones(100, dtype=torch.float64))
+    with torch.no_grad():
+        m.logits.copy_(torch.randn(3, 8, dtype=torch.float64))
+    x, jac = m(u)
+    assert ((x > 0) & (x < 1)).all()
+    us, _ = torch.sort(u[:, 0])
+    xs, _ = m(torch.stack([us, us, us], -1))
+    assert (xs[1:, 0] >= xs[:-1, 0]).all()
+    h = 1e-7
+    d = torch.ones(100, dtype=torch.float64)
+    for k in range(3):
+        up, um = u.clone(), u.clone()
+        up[:, k] += h
+        um[:, k] -= h
+        d *= (m(up)[0][:, k] - m(um)[0][:, k]) / (2 * h)
+    inside = ((u * 8 - (u * 8).round()).abs() > 1e-5).all(-1)   # away from bin edges
+    assert torch.allclose(jac[inside], d[inside], rtol=1e-6)
+
+
+def test_training_reduces_variance_and_stays_unbiased():
+    torch.manual_seed(1)
+    ndim, s0, c = 2, 0.05, 0.01
+    norm1 = s0 * math.sqrt(2 * math.pi) * (0.5 * (math.erf(0.7 / (s0 * math.sqrt(2)))
+                                                  + math.erf(0.3 / (s0 * math.sqrt(2))))) + c
+    exact = norm1 ** ndim
+
+    def fn(x):
+        return (torch.exp(-(x - 0.3) ** 2 / (2 * s0 * s0)) + c).prod(-1)
+
+    gen = torch.Generator().manual_seed(5)
+
+    def uniforms(i, n):
+        return torch.rand(n, ndim, dtype=torch.float64, generator=gen)
+
+    m, hist = adapt.train(fn, ndim, uniforms, iters=150, batch=4096, nbins=32, lr=0.1)
+    u = torch.rand(1 << 16, ndim, dtype=torch.float64, generator=gen)
+    flat = adapt.estimate(fn(u))
+    with torch.no_grad():
+        x, jac = m(u)
+    ad = adapt.estimate(fn(x) * jac)
+    assert flat[2] / ad[2] > 20
+    assert abs(ad[0] - exact) <= 4 * ad[1]
+    assert abs(flat[0] - exact) <= 4 * flat[1]
+    assert hist[-1] < 0.2 * hist[0]

@@ -13,13 +13,14 @@ LIBPATH = os.path.join(ROOT, 'paper_2106_12631_amd', 'libmg5mi.so')
 
 def declared():
     src = open(HEADER).read()
-    return re.findall(r'^\s*(?:int|const char\*)\s+(mg_\w+)\s*\(', src, re.M)
+    return re.findall(r'^\s*(?:int|int64_t|const char\*)\s+(mg_\w+)\s*\(', src, re.M)
 
 
 def test_header_declares_the_path():
     names = set(declared())
     assert {'mg_create', 'mg_destroy', 'mg_layout', 'mg_rng', 'mg_rambo', 'mg_sample',
-            'mg_sigmakin', 'mg_sigmakin_hel', 'mg_count_nonfinite', 'mg_strerror'} <= names
+            'mg_sigmakin', 'mg_sigmakin_hel', 'mg_adjoint', 'mg_count_nonfinite', 'mg_strerror',
+            'mg_xsec_stats', 'mg_xsec', 'mg_unweight', 'mg_unweight_workspace_bytes'} <= names
 
 
 @pytest.mark.skipif(not os.path.exists(LIBPATH), reason="library not built")
