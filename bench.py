@@ -82,7 +82,17 @@ def cpu_baseline(proc, seed, per_worker, workers):
         res = pool.map(_oracle_chunk, tasks)
     wall = time.perf_counter() - t0
     n = sum(c for c, _ in res)
+    per_core = sum(c / t for c, t in res) / len(res)
+    cpu_model = ''
+    try:
+        for line in open('/proc/cpuinfo'):
+            if line.startswith('model name'):
+                cpu_model = line.split(':', 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": n / wall, "unit": "MEs/s", "cores": workers, "kind": "oracle",
+            "single_core_value": per_core, "cpu": cpu_model,
             "sample": f"events 0..{n - 1} of the workload (seed {seed}): RNG + RAMBO + |M|^2, "
                       f"{workers} processes x 1 thread, {wall:.1f} s wall"}
 

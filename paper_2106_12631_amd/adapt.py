@@ -113,8 +113,18 @@ def adapt_process(engine, seed=4, iters=200, batch=1 << 14, nbins=32, lr=0.05, e
         u2 = uniforms(1, eval_batch, seed + 1)
         x, jac = m(u2)
         adapted = fn(x) * jac
-    ef = estimate(flat[torch.isfinite(flat)])
-    ea = estimate(adapted[torch.isfinite(adapted)])
-    return {"flat": {"mean": ef[0], "error": ef[1], "relative_variance": ef[2]},
-            "adapted": {"mean": ea[0], "error": ea[1], "relative_variance": ea[2]},
-            "variance_reduction": ef[2] / ea[2], "loss_history": hist, "map": m}
+    flat = flat[torch.isfinite(flat)]
+    adapted = adapted[torch.isfinite(adapted)]
+    ef, ea = estimate(flat), estimate(adapted)
+    # the raw relative variance is dominated by a few extreme weights; the
+    # capped one (both samples capped at the flat sample's 99.9% quantile)
+    # shows the bulk of the distribution
+    cap = torch.quantile(flat, 0.999)
+    cf = estimate(torch.minimum(flat, cap))[2]
+    ca = estimate(torch.minimum(adapted, cap))[2]
+    return {"flat": {"mean": ef[0], "error": ef[1], "relative_variance": ef[2],
+                     "capped_relative_variance": cf},
+            "adapted": {"mean": ea[0], "error": ea[1], "relative_variance": ea[2],
+                        "capped_relative_variance": ca},
+            "variance_reduction": ef[2] / ea[2], "capped_variance_reduction": cf / ca,
+            "loss_history": hist, "map": m}

@@ -146,6 +146,31 @@ template <typename F>
 __device__ __forceinline__ cx<dual<F>> operator*(F s, cx<dual<F>> a) { return {s * a.r, s * a.i}; }
 template <typename T>
 __device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.i, a.r}; }
+
+// Fused forms: c + a b and c - a b as four fused multiply-adds (real T), so
+// that sums of products do not round every product separately and take
+// one instruction per term.  Dual numbers fall back to the operators.
+template <typename T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) { return a * b + c; }
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <typename T>
+__device__ __forceinline__ cx<T> cmadd(cx<T> a, cx<T> b, cx<T> c) {
+  return {fmadd(a.r, b.r, fmadd(-a.i, b.i, c.r)), fmadd(a.r, b.i, fmadd(a.i, b.r, c.i))};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmsub(cx<T> a, cx<T> b, cx<T> c) {
+  return {fmadd(-a.r, b.r, fmadd(a.i, b.i, c.r)), fmadd(-a.r, b.i, fmadd(-a.i, b.r, c.i))};
+}
+// real scalar s: c + s a, c - s a
+template <typename T>
+__device__ __forceinline__ cx<T> rmadd(T s, cx<T> a, cx<T> c) {
+  return {fmadd(s, a.r, c.r), fmadd(s, a.i, c.i)};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> rmsub(T s, cx<T> a, cx<T> c) {
+  return {fmadd(-s, a.r, c.r), fmadd(-s, a.i, c.i)};
+}
 template <typename T>
 __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.r, -a.i}; }
 
@@ -316,43 +341,43 @@ __device__ __forceinline__ void slash_blocks(const cx<T> V[4], blk<T>& s, blk<T>
 // column: M x
 template <typename T>
 __device__ __forceinline__ void mcol(const blk<T>& m, cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
-  y0 = m.a * x0 + m.b * x1;
-  y1 = m.c * x0 + m.d * x1;
+  y0 = cmadd(m.b, x1, m.a * x0);
+  y1 = cmadd(m.d, x1, m.c * x0);
 }
 // row: x M
 template <typename T>
 __device__ __forceinline__ void mrow(const blk<T>& m, cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
-  y0 = x0 * m.a + x1 * m.c;
-  y1 = x0 * m.b + x1 * m.d;
+  y0 = cmadd(x1, m.c, x0 * m.a);
+  y1 = cmadd(x1, m.d, x0 * m.b);
 }
 
 // column: (s.K) x with s.K = [[K0-K3, -(K1 - i K2)], [-(K1 + i K2), K0+K3]]
 template <typename T>
 __device__ __forceinline__ void sK_col(const T K[4], cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
   const cx<T> m01{-K[1], K[2]}, m10{-K[1], -K[2]};
-  y0 = (K[0] - K[3]) * x0 + m01 * x1;
-  y1 = m10 * x0 + (K[0] + K[3]) * x1;
+  y0 = cmadd(m01, x1, (K[0] - K[3]) * x0);
+  y1 = cmadd(m10, x0, (K[0] + K[3]) * x1);
 }
 // column: (sb.K) x with sb.K = [[K0+K3, K1 - i K2], [K1 + i K2, K0-K3]]
 template <typename T>
 __device__ __forceinline__ void sbK_col(const T K[4], cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
   const cx<T> m01{K[1], -K[2]}, m10{K[1], K[2]};
-  y0 = (K[0] + K[3]) * x0 + m01 * x1;
-  y1 = m10 * x0 + (K[0] - K[3]) * x1;
+  y0 = cmadd(m01, x1, (K[0] + K[3]) * x0);
+  y1 = cmadd(m10, x0, (K[0] - K[3]) * x1);
 }
 // row: x (s.K)
 template <typename T>
 __device__ __forceinline__ void sK_row(const T K[4], cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
   const cx<T> m01{-K[1], K[2]}, m10{-K[1], -K[2]};
-  y0 = (K[0] - K[3]) * x0 + x1 * m10;
-  y1 = x0 * m01 + (K[0] + K[3]) * x1;
+  y0 = cmadd(x1, m10, (K[0] - K[3]) * x0);
+  y1 = cmadd(x0, m01, (K[0] + K[3]) * x1);
 }
 // row: x (sb.K)
 template <typename T>
 __device__ __forceinline__ void sbK_row(const T K[4], cx<T> x0, cx<T> x1, cx<T>& y0, cx<T>& y1) {
   const cx<T> m01{K[1], -K[2]}, m10{K[1], K[2]};
-  y0 = (K[0] + K[3]) * x0 + x1 * m10;
-  y1 = x0 * m01 + (K[0] - K[3]) * x1;
+  y0 = cmadd(x1, m10, (K[0] + K[3]) * x0);
+  y1 = cmadd(x0, m01, (K[0] - K[3]) * x1);
 }
 
 template <typename T, typename R>
@@ -367,11 +392,11 @@ __device__ __forceinline__ R msq(const R K[4]) {
 
 template <typename T>
 __device__ __forceinline__ cx<T> mdot(const cx<T> a[4], const cx<T> b[4]) {
-  return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  return cmsub(a[3], b[3], cmsub(a[2], b[2], cmsub(a[1], b[1], a[0] * b[0])));
 }
 template <typename T>
 __device__ __forceinline__ cx<T> mdot(const T k[4], const cx<T> b[4]) {
-  return k[0] * b[0] - k[1] * b[1] - k[2] * b[2] - k[3] * b[3];
+  return rmsub(k[3], b[3], rmsub(k[2], b[2], rmsub(k[1], b[1], k[0] * b[0])));
 }
 
 // ---------------------------------------------------------------------------
@@ -424,7 +449,7 @@ __device__ __forceinline__ void ffv_cur_vm(const cx<T> F[4], const cx<T> G[4], b
   to_T(K, k);
   const cx<T> kj = (T)(1.0 / (mass * mass)) * mdot(k, J);
   const cx<T> d = inv_den<T>(msq(K) - mass * mass, R(mass * width));
-  for (int m = 0; m < 4; ++m) out[m] = d * (J[m] - k[m] * kj);
+  for (int m = 0; m < 4; ++m) out[m] = d * rmsub(k[m], kj, J[m]);
 }
 
 // flow-in fermion current: i(K-slash + m)/D * i V-slash (cL P_L + cR P_R) G
@@ -446,10 +471,10 @@ __device__ __forceinline__ void ffv_cur_fin(const cx<T> V[4], const cx<T> G[4], 
   sK_col(k, f2, f3, y0, y1);
   sbK_col(k, f0, f1, y2, y3);
   const cx<T> d = -inv_den<T>(msq(K) - m * m, R(m * w));  // i * i = -1
-  out[0] = d * (y0 + mm * f0);
-  out[1] = d * (y1 + mm * f1);
-  out[2] = d * (y2 + mm * f2);
-  out[3] = d * (y3 + mm * f3);
+  out[0] = d * rmadd(mm, f0, y0);
+  out[1] = d * rmadd(mm, f1, y1);
+  out[2] = d * rmadd(mm, f2, y2);
+  out[3] = d * rmadd(mm, f3, y3);
 }
 
 // flow-out fermion current: F i V-slash (cL P_L + cR P_R) * i(-K-slash + m)/D
@@ -472,10 +497,10 @@ __device__ __forceinline__ void ffv_cur_fout(const cx<T> F[4], const cx<T> V[4],
   sbK_row(k, f2, f3, y0, y1);
   sK_row(k, f0, f1, y2, y3);
   const cx<T> d = -inv_den<T>(msq(K) - m * m, R(m * w));
-  out[0] = d * (mm * f0 - y0);
-  out[1] = d * (mm * f1 - y1);
-  out[2] = d * (mm * f2 - y2);
-  out[3] = d * (mm * f3 - y3);
+  out[0] = d * rmadd(mm, f0, -y0);
+  out[1] = d * rmadd(mm, f1, -y1);
+  out[2] = d * rmadd(mm, f2, -y2);
+  out[3] = d * rmadd(mm, f3, -y3);
 }
 
 // ---------------------------------------------------------------------------
@@ -500,8 +525,8 @@ __device__ __forceinline__ void vvv_cur(const cx<T> A[4], const R KA[4], const c
   to_T(dk, tdk);
   const cx<T> ca = mdot(tqa, B), cb = mdot(tqb, A), ab = mdot(A, B);
   // (-i g / K^2) [...]
-  const cx<T> pre{(T)0.0, (T)(-1.0 / msq(K)) * g};
-  for (int m = 0; m < 4; ++m) out[m] = pre * (A[m] * ca + tdk[m] * ab + B[m] * cb);
+  const T pim = (T)(-1.0 / msq(K)) * g;
+  for (int m = 0; m < 4; ++m) out[m] = pim * times_i(rmadd(tdk[m], ab, cmadd(B[m], cb, A[m] * ca)));
 }
 
 // four-gluon current, structure s (1, 2, 3), legs (out, X, Y, Z):
@@ -513,13 +538,13 @@ __device__ __forceinline__ void vvvv_cur(const cx<T> X[4], const cx<T> Y[4], con
   const T pre = (T)(-1.0 / msq(K)) * g2;
   if (S == 1) {
     const cx<T> xz = pre * mdot(X, Z), xy = pre * mdot(X, Y);
-    for (int m = 0; m < 4; ++m) out[m] = Y[m] * xz - Z[m] * xy;
+    for (int m = 0; m < 4; ++m) out[m] = cmsub(Z[m], xy, Y[m] * xz);
   } else if (S == 2) {
     const cx<T> yz = pre * mdot(Y, Z), xy = pre * mdot(X, Y);
-    for (int m = 0; m < 4; ++m) out[m] = X[m] * yz - Z[m] * xy;
+    for (int m = 0; m < 4; ++m) out[m] = cmsub(Z[m], xy, X[m] * yz);
   } else {
     const cx<T> yz = pre * mdot(Y, Z), xz = pre * mdot(X, Z);
-    for (int m = 0; m < 4; ++m) out[m] = X[m] * yz - Y[m] * xz;
+    for (int m = 0; m < 4; ++m) out[m] = cmsub(Y[m], xz, X[m] * yz);
   }
 }
 
