@@ -62,77 +62,6 @@ __global__ void __launch_bounds__(64)
   if (mew) mew[i] = me * inv_iden * w;
 }
 
-// Helicity-parallel form: 2^npar lanes per event (eemumu, ggtt: 16, ggttg:
-// 32), lane h of an event's group computes helicity h (all helicities; the
-// ones helicity filtering drops are exact zeros), the group sums |M|^2 and
-// the momentum adjoints with butterfly shuffles, and lane j < 4 nparf of the
-// group computes the Jacobian column dp/dr_j (one dual RAMBO pass) and
-// writes df/dr_j.  Every lane of a group takes part in the shuffles: groups
-// past nevt repeat the last event and store nothing.
-template <class P, int NF, typename T>
-__global__ void __launch_bounds__(64)
-    adjoint_hpl_kernel(const double* __restrict__ rnd, int64_t nevt, RamboArgs ra,
-                       Couplings<T> c, double inv_iden, const double* __restrict__ gbar,
-                       double* __restrict__ grad_rnd, double* __restrict__ grad_logw,
-                       double* __restrict__ mew) {
-  using D = dual<double>;
-  constexpr int NR = 4 * NF, NP = NF + 2, LPE = 1 << NP;
-  static_assert(64 % LPE == 0 && LPE >= NR, "helicity groups must tile the wave");
-  const int lane = threadIdx.x, sub = lane % LPE;
-  const int64_t i = (int64_t)blockIdx.x * (64 / LPE) + lane / LPE;
-  const bool valid = i < nevt;
-  const int64_t il = valid ? i : nevt - 1;
-  double r[NR];
-#pragma unroll
-  for (int k = 0; k < NR; ++k) r[k] = rnd[aosoa_rnd(il, k, NR)];
-  double p[NP][4], w;
-  rambo<NF>(r, ra, p, w);
-  double pb[NP][4];
-#pragma unroll
-  for (int l = 0; l < NP; ++l)
-#pragma unroll
-    for (int m = 0; m < 4; ++m) pb[l][m] = 0.0;
-  double me = P::adjoint(p, (unsigned)sub, c, pb);
-#pragma unroll
-  for (int off = LPE / 2; off > 0; off >>= 1) {
-    me += __shfl_xor(me, off);
-#pragma unroll
-    for (int l = 2; l < NP; ++l)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) pb[l][m] += __shfl_xor(pb[l][m], off);
-  }
-  if (!valid) return;
-  if (sub < NR) {
-    const int j = sub;
-    D rd[NR], pd[NP][4], wd;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) rd[k] = D(r[k], k == j ? 1.0 : 0.0);
-    rambo<NF>(rd, ra, pd, wd);
-    double s = 0.0;
-#pragma unroll
-    for (int l = 2; l < NP; ++l)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) s += pb[l][m] * pd[l][m].d;
-    const double g = gbar ? gbar[i] : 1.0;
-    const double df = inv_iden * (w * s + me * wd.d);
-    grad_rnd[aosoa_rnd(i, j, NR)] = g * df;
-    if (grad_logw) grad_logw[aosoa_rnd(i, j, NR)] = wd.d / wd.v;
-  }
-  if (sub == 0 && mew) mew[i] = me * inv_iden * w;
-}
-
-template <class P, int NF, typename T>
-int adjoint_hpl_launch(const MeArgs& a, const RamboArgs& ra, const Couplings<T>& c,
-                       const double* rnd, int64_t nevt, const double* gbar, double* grad_rnd,
-                       double* grad_logw, double* mew, hipStream_t s) {
-  constexpr int EPW = 64 >> (NF + 2);  // events per wave
-  const int64_t g = (nevt + EPW - 1) / EPW;
-  if (g > 0x7FFFFFFF) return -1;
-  adjoint_hpl_kernel<P, NF, T><<<(unsigned)g, 64, 0, s>>>(rnd, nevt, ra, c, a.inv_iden, gbar,
-                                                          grad_rnd, grad_logw, mew);
-  return 0;
-}
-
 template <class P, int NF, typename T>
 int adjoint_launch(const MeArgs& a, const RamboArgs& ra, const Couplings<T>& c, const double* rnd,
                    int64_t nevt, const double* gbar, double* grad_rnd, double* grad_logw,

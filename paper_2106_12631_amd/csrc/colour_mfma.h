@@ -94,7 +94,19 @@ __device__ __forceinline__ float combine_halves(float part_lo, float part_hi, in
 template <int NCOL>
 struct ColourMfmaF32 {
   static constexpr int KB = (NCOL + 1) / 2;  // K blocks of 2
+  using Word = float;                        // one A-operand register per K block
   float a[KB];
+
+  // the A operands can be parked in LDS (tab[kb][lane]) between colour sums
+  // so that they take no registers across the amplitude code
+  __device__ __forceinline__ void save(Word* tab, int lane) const {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) tab[kb * 64 + lane] = a[kb];
+  }
+  __device__ __forceinline__ void restore(const Word* tab, int lane) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) a[kb] = tab[kb * 64 + lane];
+  }
 
   // cnum: the NCOL x NCOL integer numerators of C, row-major
   __device__ __forceinline__ void init(const int* cnum, int lane) {
@@ -133,7 +145,17 @@ struct ColourMfmaBf16 {
   static constexpr int G = (NCOL + 7) / 8;  // colour groups of 8
   static constexpr int NCH = 3 * G;         // chunks (split, group) of 8 K entries
   static constexpr int KB = (NCH + 1) / 2;  // K blocks of 16 (two chunks)
+  using Word = uintx4;
   bf16x8 a[KB];
+
+  __device__ __forceinline__ void save(Word* tab, int lane) const {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) tab[kb * 64 + lane] = __builtin_bit_cast(uintx4, a[kb]);
+  }
+  __device__ __forceinline__ void restore(const Word* tab, int lane) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) a[kb] = __builtin_bit_cast(bf16x8, tab[kb * 64 + lane]);
+  }
 
   __device__ __forceinline__ void init(const int* cnum, int lane) {
     const int m = lane & 31, kh = lane >> 5;

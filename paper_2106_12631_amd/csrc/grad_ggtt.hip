@@ -24,19 +24,11 @@ struct A32_ggtt {
 int launch_grad_ggtt(int prec, const MeArgs& a, const RamboArgs& ra, const double* rnd, int64_t nevt,
                    const double* gbar, double* grad_rnd, double* grad_logw, double* mew,
                    hipStream_t s) {
-#ifndef MG_ADJOINT_HPL
   if (prec == 0)
     return adjoint_launch<A64_ggtt, 2, double>(a, ra, a.c64, rnd, nevt, gbar, grad_rnd, grad_logw,
                                                 mew, s);
   return adjoint_launch<A32_ggtt, 2, float>(a, ra, a.c32, rnd, nevt, gbar, grad_rnd, grad_logw,
                                              mew, s);
-#else
-  if (prec == 0)
-    return adjoint_hpl_launch<A64_ggtt, 2, double>(a, ra, a.c64, rnd, nevt, gbar, grad_rnd,
-                                                    grad_logw, mew, s);
-  return adjoint_hpl_launch<A32_ggtt, 2, float>(a, ra, a.c32, rnd, nevt, gbar, grad_rnd,
-                                                 grad_logw, mew, s);
-#endif
 }
 
 }  // namespace mg

@@ -23,10 +23,10 @@ struct P_ggttgg {
 
 int launch_sigmakin_ggttgg_f32(const MeArgs& a, const double* mom, int64_t nevt, double* me,
                               const double* wgt, double* evtw, double* mehel, hipStream_t s) {
-#ifdef MG_HPL_F32
-  return sigmakin_hpl_launch<P_ggttgg, float, 64>(a, a.c32, mom, nevt, me, wgt, evtw, mehel, s);
-#else
+#ifdef MG_EVENT_PER_LANE_F32
   return sigmakin_launch<P_ggttgg, float, 64>(a, a.c32, mom, nevt, me, wgt, evtw, mehel, s);
+#else
+  return sigmakin_hpl_launch<P_ggttgg, float, 64>(a, a.c32, mom, nevt, me, wgt, evtw, mehel, s);
 #endif
 }
 

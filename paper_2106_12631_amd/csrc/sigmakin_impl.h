@@ -9,6 +9,18 @@
 
 namespace mg {
 
+// Workgroups are handed to the 8 XCDs of the chip in turn (block b to XCD
+// b % 8), each with its own L2.  With one event per block, consecutive
+// events share the 64-byte lines of the AoSoA momenta, so the event of
+// block b is chosen to give XCD x one contiguous range of events, walked in
+// dispatch order: a bijection of [0, nblocks).
+__device__ __forceinline__ int64_t xcd_event(int64_t b, int64_t nblocks) {
+  constexpr int NXCD = 8;
+  const int64_t q = nblocks / NXCD, r = nblocks % NXCD;
+  const int64_t x = b % NXCD, k = b / NXCD;
+  return x * q + (x < r ? x : r) + k;
+}
+
 template <class P>
 __device__ __forceinline__ void load_event(const double* __restrict__ mom, int64_t i,
                                            double (&p)[P::NPAR][4]) {
@@ -63,8 +75,13 @@ __global__ void __launch_bounds__(64)
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   const bool valid = i < nevt;
   const int64_t il = valid ? i : nevt - 1;
-  CS<P::NCOL> cs;
+  // the matrix-core A operands (the colour matrix) wait in LDS while the
+  // amplitude code runs and are reloaded for each colour sum
+  using CSN = CS<P::NCOL>;
+  __shared__ typename CSN::Word tab[CSN::KB * 64];
+  CSN cs;
   cs.init(P::cnum(), lane);
+  cs.save(tab, lane);
   const double scale = inv_iden / P::CDEN;
   double acc = 0.0;
 #pragma nounroll
@@ -75,6 +92,9 @@ __global__ void __launch_bounds__(64)
     load_event<P>(mom, iq, q);
     cx<float> J[P::NCOL];
     P::template jamps<float>(q, hl.code[k], c, J);
+    int lt = lane;
+    asm volatile("" : "+v"(lt));
+    cs.restore(tab, lt);
     acc += (double)cs.sum(J, lane);
   }
   if (valid) {
@@ -117,7 +137,7 @@ __global__ void __launch_bounds__(64)
                         const double* __restrict__ wgt, double* __restrict__ evtw,
                         double* __restrict__ mehel, Couplings<T> c, double inv_iden) {
   static_assert((1 << P::NPAR) == 64, "one helicity per lane of a wave64");
-  const int64_t i = blockIdx.x;
+  const int64_t i = xcd_event(blockIdx.x, nevt);
   const unsigned h = threadIdx.x;
   double q[P::NPAR][4];
   load_event<P>(mom, i, q);
@@ -157,14 +177,17 @@ __global__ void __launch_bounds__(64)
                               double* __restrict__ me, const double* __restrict__ wgt,
                               double* __restrict__ evtw, Couplings<float> c, double inv_iden) {
   static_assert((1 << P::NPAR) == 64, "one helicity per lane of a wave64");
-  const int64_t i = blockIdx.x;
+  const int64_t i = xcd_event(blockIdx.x, nevt);
   const int lane = threadIdx.x;
-  CS<P::NCOL> cs;
-  cs.init(P::cnum(), lane);
   double q[P::NPAR][4];
   load_event<P>(mom, i, q);
   cx<float> J[P::NCOL];
   P::template jamps<float, true>(q, (unsigned)lane, c, J);
+  // the colour matrix operands are formed only now, after the amplitudes
+  int lt = lane;
+  asm volatile("" : "+v"(lt));
+  CS<P::NCOL> cs;
+  cs.init(P::cnum(), lt);
   double v = (double)cs.sum(J, lane);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);

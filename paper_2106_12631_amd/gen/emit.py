@@ -684,12 +684,15 @@ def emit_adjoint_body(pd, coefs, order, bils, need, budget):
     return L, execd
 
 
-# register budget in live wavefunctions (4 complex each) per precision:
-# FP64 wavefunctions take 16 VGPRs, FP32 ones 8; the colour-flow amplitudes
-# and the momenta stay live besides them.  'f32m' is the FP32 body used by
-# the kernel whose colour sum runs on the matrix cores (its operands need
-# registers too).
-BUDGET = {'f64': 12, 'f32': 36, 'f32m': 28, 'a64': 8, 'a32': 12}
+# register budget in live wavefunctions (4 complex each) per precision, the
+# measured best for gg -> t t~ g g on gfx950 (FP64 wavefunctions take 16
+# VGPRs, FP32 ones 8; the colour-flow amplitudes stay live besides them).
+# FP64 16, one helicity per lane: fewer recomputations outweigh a few
+# hundred bytes of spills (12: 16.8, 14: 18.3, 16: 18.7 M MEs/s).  FP32 12,
+# one helicity per lane, fits 256 registers: two waves per SIMD (27.1 M
+# MEs/s; 10: 22.6).  'f32m' is the FP32 body of the event-per-lane kernel
+# whose colour sum runs on the matrix cores (28: 23.8, 36: 26.1).
+BUDGET = {'f64': 16, 'f32': 12, 'f32m': 36, 'a64': 8, 'a32': 12}
 # processes with a generated reverse-mode (adjoint) body for the gradient kernel
 GRAD_PROCESSES = ('eemumu', 'ggtt', 'ggttg')
 OPT_ITERS = 2500
