@@ -27,15 +27,16 @@ PEAK_FP32_VALU_UNPACKED = 78.6e12  # FLOP/s without packed-FP32 instructions (no
 # ----------------------------------------------------------------------------- HBM traffic
 def kernel_source_hash(proc):
     """sha256 over everything that defines the SIGMAKIN kernels of proc: the
-    shared headers, the process's kernel sources, its generated code and the
-    compiler flags.  HBM counters recorded under profiles/ are reported only
+    headers they use, the process's kernel sources, its generated code and
+    the compiler flags.  HBM counters recorded under profiles/ are reported only
     while this hash matches the one they were taken with."""
     import hashlib
     sys.path.insert(0, os.path.join(ROOT, 'paper_2106_12631_amd'))
     from paper_2106_12631_amd import build as _build
     csrc = os.path.join(ROOT, 'paper_2106_12631_amd', 'csrc')
-    names = sorted(n for n in os.listdir(csrc)
-                   if n.endswith('.h') or (n.startswith(f'sigmakin_{proc}_') and n.endswith('.hip')))
+    shared = ['colour_mfma.h', 'common.h', 'helas.h', 'internal.h', 'sigmakin_impl.h']
+    names = shared + sorted(n for n in os.listdir(csrc)
+                            if n.startswith(f'sigmakin_{proc}_') and n.endswith('.hip'))
     h = hashlib.sha256()
     for n in names + [os.path.join('generated', f'{proc}.inc')]:
         h.update(n.encode())

@@ -25,7 +25,7 @@ template <typename T>
 __device__ __forceinline__ cx<T> cdot4(const cx<T> a[4], const cx<T> b[4]) {
   cx<T> s = conj(a[0]) * b[0];
 #pragma unroll
-  for (int c = 1; c < 4; ++c) s = cmadd(conj(a[c]), b[c], s);
+  for (int c = 1; c < 4; ++c) s = s + conj(a[c]) * b[c];
   return s;
 }
 // Re(conj(a) b)
@@ -45,14 +45,14 @@ __device__ __forceinline__ void adj_bilinear(const cx<T> F[4], const cx<T> G[4],
   const cx<T> a01 = cR * (Jb[1] + ia), a10 = cR * (Jb[1] - ia);
   const cx<T> b00 = cL * (Jb[0] - Jb[3]), b11 = cL * (Jb[0] + Jb[3]);
   const cx<T> b01 = -(cL * (Jb[1] + ia)), b10 = -(cL * (Jb[1] - ia));
-  Fb[0] = cmadd(conj(G[3]), a01, cmadd(conj(G[2]), a00, Fb[0]));
-  Fb[1] = cmadd(conj(G[2]), a10, cmadd(conj(G[3]), a11, Fb[1]));
-  Fb[2] = cmadd(conj(G[1]), b01, cmadd(conj(G[0]), b00, Fb[2]));
-  Fb[3] = cmadd(conj(G[0]), b10, cmadd(conj(G[1]), b11, Fb[3]));
-  Gb[0] = cmadd(conj(F[3]), b10, cmadd(conj(F[2]), b00, Gb[0]));
-  Gb[1] = cmadd(conj(F[2]), b01, cmadd(conj(F[3]), b11, Gb[1]));
-  Gb[2] = cmadd(conj(F[1]), a10, cmadd(conj(F[0]), a00, Gb[2]));
-  Gb[3] = cmadd(conj(F[0]), a01, cmadd(conj(F[1]), a11, Gb[3]));
+  Fb[0] = Fb[0] + conj(G[2]) * a00 + conj(G[3]) * a01;
+  Fb[1] = Fb[1] + conj(G[3]) * a11 + conj(G[2]) * a10;
+  Fb[2] = Fb[2] + conj(G[0]) * b00 + conj(G[1]) * b01;
+  Fb[3] = Fb[3] + conj(G[1]) * b11 + conj(G[0]) * b10;
+  Gb[0] = Gb[0] + conj(F[2]) * b00 + conj(F[3]) * b10;
+  Gb[1] = Gb[1] + conj(F[3]) * b11 + conj(F[2]) * b01;
+  Gb[2] = Gb[2] + conj(F[0]) * a00 + conj(F[1]) * a10;
+  Gb[3] = Gb[3] + conj(F[1]) * a11 + conj(F[0]) * a01;
 }
 
 // a = i mdot(B, V): add Bb and Vb
