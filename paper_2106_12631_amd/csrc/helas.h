@@ -174,10 +174,22 @@ __device__ __forceinline__ cx<T> rmsub(T s, cx<T> a, cx<T> c) {
 template <typename T>
 __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.r, -a.i}; }
 
+// Reciprocal of a propagator denominator: the hardware estimate refined by
+// two Newton steps r <- r + r (1 - x r), within an ulp or two of 1/x for the
+// finite, non-zero, normal x that reach it (squared momentum sums minus
+// squared masses).  Other real types (dual numbers) divide.
+template <typename R>
+__device__ __forceinline__ R recip(R x) { return R(1.0) / x; }
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+
 // 1 / (re + i im) formed in R, rounded to T
 template <typename T, typename R>
 __device__ __forceinline__ cx<T> inv_den(R re, R im) {
-  const R n = 1.0 / (re * re + im * im);
+  const R n = recip(re * re + im * im);
   return cx<T>{(T)(re * n), (T)(-im * n)};
 }
 
@@ -433,7 +445,7 @@ __device__ __forceinline__ void ffv_cur_v0(const cx<T> F[4], const cx<T> G[4], b
                                            base_t<T> cR, const R K[4], cx<T> out[4]) {
   cx<T> J[4];
   ffv_bilinear(F, G, cL, cR, J);
-  const T rk = (T)(1.0 / msq(K));
+  const T rk = (T)recip(msq(K));
   for (int m = 0; m < 4; ++m) out[m] = rk * J[m];
 }
 
@@ -447,7 +459,7 @@ __device__ __forceinline__ void ffv_cur_vm(const cx<T> F[4], const cx<T> G[4], b
   ffv_bilinear(F, G, cL, cR, J);
   T k[4];
   to_T(K, k);
-  const cx<T> kj = (T)(1.0 / (mass * mass)) * mdot(k, J);
+  const cx<T> kj = (T)recip(mass * mass) * mdot(k, J);
   const cx<T> d = inv_den<T>(msq(K) - mass * mass, R(mass * width));
   for (int m = 0; m < 4; ++m) out[m] = d * rmsub(k[m], kj, J[m]);
 }
@@ -525,7 +537,7 @@ __device__ __forceinline__ void vvv_cur(const cx<T> A[4], const R KA[4], const c
   to_T(dk, tdk);
   const cx<T> ca = mdot(tqa, B), cb = mdot(tqb, A), ab = mdot(A, B);
   // (-i g / K^2) [...]
-  const T pim = (T)(-1.0 / msq(K)) * g;
+  const T pim = (T)(-recip(msq(K))) * g;
   for (int m = 0; m < 4; ++m) out[m] = pim * times_i(rmadd(tdk[m], ab, cmadd(B[m], cb, A[m] * ca)));
 }
 
@@ -535,7 +547,7 @@ __device__ __forceinline__ void vvv_cur(const cx<T> A[4], const R KA[4], const c
 template <int S, typename T, typename R>
 __device__ __forceinline__ void vvvv_cur(const cx<T> X[4], const cx<T> Y[4], const cx<T> Z[4],
                                          const R K[4], base_t<T> g2, cx<T> out[4]) {
-  const T pre = (T)(-1.0 / msq(K)) * g2;
+  const T pre = (T)(-recip(msq(K))) * g2;
   if (S == 1) {
     const cx<T> xz = pre * mdot(X, Z), xy = pre * mdot(X, Y);
     for (int m = 0; m < 4; ++m) out[m] = cmsub(Z[m], xy, Y[m] * xz);
