@@ -19,7 +19,8 @@
 // operands from the lane's own values: with a from every lane and b from
 // every lane, swap(a, b) returns r0 = (a of lanes 0-31, b of lanes 0-31
 // moved up) -- the lo tile -- and r1 = (a of lanes 32-63 moved down, b of
-// lanes 32-63) -- the hi tile.  No LDS and no barrier is involved.
+// lanes 32-63) -- the hi tile.  The operands need no LDS staging and no
+// barrier (the kernels may park the constant A operands in LDS).
 //
 // Two forms:
 //   ColourMfmaF32   FP32 operands (C integer numerators exact in FP32),

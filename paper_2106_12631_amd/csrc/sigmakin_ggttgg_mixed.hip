@@ -23,20 +23,12 @@ struct P_ggttgg {
 
 int launch_sigmakin_ggttgg_mfma_f32(const MeArgs& a, const double* mom, int64_t nevt, double* me,
                                 const double* wgt, double* evtw, hipStream_t s) {
-#ifdef MG_HPL_MIXED
-  return sigmakin_mixed_hpl_launch<P_ggttgg, ColourMfmaF32>(a, mom, nevt, me, wgt, evtw, s);
-#else
   return sigmakin_mixed_launch<P_ggttgg, ColourMfmaF32>(a, mom, nevt, me, wgt, evtw, s);
-#endif
 }
 
 int launch_sigmakin_ggttgg_mfma_bf16(const MeArgs& a, const double* mom, int64_t nevt, double* me,
                                  const double* wgt, double* evtw, hipStream_t s) {
-#ifdef MG_HPL_MIXED
-  return sigmakin_mixed_hpl_launch<P_ggttgg, ColourMfmaBf16>(a, mom, nevt, me, wgt, evtw, s);
-#else
   return sigmakin_mixed_launch<P_ggttgg, ColourMfmaBf16>(a, mom, nevt, me, wgt, evtw, s);
-#endif
 }
 
 }  // namespace mg

@@ -1,7 +1,13 @@
-// SIGMAKIN kernels for one process (Sec. II, Sec. IV.b): one event per lane,
-// the loop over the kept helicities inside the lane; per helicity the
+// SIGMAKIN kernels for one process (Sec. II, Sec. IV.b).  Per helicity the
 // generated straight-line code builds the colour-flow amplitudes and the
-// colour sum gives the helicity's |M|^2, accumulated in FP64.
+// colour sum gives the helicity's |M|^2; the helicity sum is in FP64.
+//   sigmakin_kernel          one event per lane, the loop over the kept
+//                            helicities inside the lane (the paper's layout);
+//   sigmakin_hpl_kernel      one event per wave, one helicity per lane (64
+//                            helicities): wave-uniform momenta in scalar
+//                            registers, helicity sum by wave reduction;
+//   sigmakin_mixed_kernel    event per lane with the colour sum on the
+//                            matrix cores (colour_mfma.h).
 #pragma once
 #include "colour_mfma.h"
 #include "common.h"
@@ -166,47 +172,6 @@ int sigmakin_hpl_launch(const MeArgs& a, const Couplings<T>& c, const double* mo
     return 0;
   }
   return sigmakin_launch<P, T, BS>(a, c, mom, nevt, me, wgt, evtw, mehel, s);
-}
-
-// Mixed precision, one event per wave and one helicity per lane: the 64
-// helicities' colour-flow amplitudes are the 64 columns of the MFMA colour
-// sum, whose per-lane results are then summed over the wave in FP64.
-template <class P, template <int> class CS>
-__global__ void __launch_bounds__(64)
-    sigmakin_mixed_hpl_kernel(const double* __restrict__ mom, int64_t nevt,
-                              double* __restrict__ me, const double* __restrict__ wgt,
-                              double* __restrict__ evtw, Couplings<float> c, double inv_iden) {
-  static_assert((1 << P::NPAR) == 64, "one helicity per lane of a wave64");
-  const int64_t i = xcd_event(blockIdx.x, nevt);
-  const int lane = threadIdx.x;
-  double q[P::NPAR][4];
-  load_event<P>(mom, i, q);
-  cx<float> J[P::NCOL];
-  P::template jamps<float, true>(q, (unsigned)lane, c, J);
-  // the colour matrix operands are formed only now, after the amplitudes
-  int lt = lane;
-  asm volatile("" : "+v"(lt));
-  CS<P::NCOL> cs;
-  cs.init(P::cnum(), lt);
-  double v = (double)cs.sum(J, lane);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  if (lane == 0) {
-    const double m = v * (inv_iden / P::CDEN);
-    if (me) me[i] = m;
-    if (evtw) evtw[i] = m * wgt[i];
-  }
-}
-
-template <class P, template <int> class CS>
-int sigmakin_mixed_hpl_launch(const MeArgs& a, const double* mom, int64_t nevt, double* me,
-                              const double* wgt, double* evtw, hipStream_t s) {
-  if (a.hel.n == (1 << P::NPAR) && nevt > 0 && nevt <= 0x7FFFFFFF) {
-    sigmakin_mixed_hpl_kernel<P, CS><<<(unsigned)nevt, 64, 0, s>>>(mom, nevt, me, wgt, evtw,
-                                                                  a.c32, a.inv_iden);
-    return 0;
-  }
-  return sigmakin_mixed_launch<P, CS>(a, mom, nevt, me, wgt, evtw, s);
 }
 
 }  // namespace mg
