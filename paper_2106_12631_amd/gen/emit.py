@@ -333,7 +333,7 @@ def _ext_code(n, name, npar):
     return f"cx<T> {name}[4]; {fn[0]}<T>({p}, {mass}, {hel}, {fn[1]}, {name});", FLOPS[routine]
 
 
-def emit_body(pd, coefs, order, bils, need, budget, evict_ext=False):
+def emit_body(pd, coefs, order, bils, need, budget):
     """Straight-line body of jamps() for one register budget (in live
     wavefunctions).  Wavefunctions are computed on first use; when the
     budget is full the live one whose next use is farthest is dropped
@@ -375,7 +375,7 @@ def emit_body(pd, coefs, order, bils, need, budget, evict_ext=False):
 
     def evict(pos, pinned):
         while len(live) >= budget:
-            cand = [x for x in live if x not in pinned and (evict_ext or live[x][1].op[0] != 'ext')]
+            cand = [x for x in live if x not in pinned and live[x][1].op[0] != 'ext']
             if not cand:
                 return
             victim = max(cand, key=lambda x: next_use(x, pos))
@@ -769,8 +769,7 @@ def generate(name, orders=None):
     for prec, T, Rt, Ct in variants:
         budget = _budget(prec)
         order = orders[(name, budget)]
-        body, algo, execd, peak, rec = emit_body(pd, coefs, order, bils, need, budget,
-                                                 evict_ext=False)
+        body, algo, execd, peak, rec = emit_body(pd, coefs, order, bils, need, budget)
         stats[prec] = dict(flops_amp_per_hel=algo, flops_executed_per_hel=execd,
                            peak_live_wavefunctions=peak, recomputed=rec)
         jparam = f"cx<{T}> (&J)[{ncol}]"
