@@ -14,8 +14,9 @@
  *     be 8-byte aligned (MG_EALIGN otherwise).
  *   - `stream` is a hipStream_t cast to void* (NULL = the null stream).
  *     Calls enqueue work on it and return without synchronising, except
- *     mg_create (which runs a small helicity-filtering pass and waits for
- *     it) and mg_count_nonfinite's optional host copy.
+ *     mg_create (which allocates, runs and frees a small helicity-filtering
+ *     pass and waits for it); mg_xsec and mg_unweight_workspace_bytes are
+ *     host arithmetic only.
  *   - A handle is immutable after mg_create; any number of streams may use
  *     it concurrently with disjoint outputs.
  *

@@ -54,6 +54,17 @@ def relative_second_moment(F):
     return (F * F).mean() / (m * m)
 
 
+def kl_divergence(F):
+    """KL(p || q) up to a constant for the target density p = f / I and the
+    sampling density q = 1 / |dg/du| of the map: E_u[(F/I) log(F/I)] with
+    I estimated by the batch mean (held fixed in the gradient)."""
+    r = F / F.mean().detach()
+    return (r * torch.log(r.clamp_min(1e-300))).mean()
+
+
+LOSSES = {'variance': relative_second_moment, 'kl': kl_divergence}
+
+
 def estimate(F):
     """Mean, its standard error and the relative variance of a weight sample."""
     n = F.numel()
@@ -63,11 +74,13 @@ def estimate(F):
 
 
 def train(fn, ndim, uniforms, iters=200, batch=1 << 14, nbins=32, lr=0.05, device=None,
-          log=None, clip=0.995):
+          log=None, clip=0.995, loss='variance'):
     """Train a WarpMap for the integrand fn (a differentiable torch function
     of (N, ndim) points in (0, 1) returning (N,) weights); uniforms(i, n)
-    returns the i-th batch of n uniforms.  Returns the map and the loss
-    history (relative second moment per iteration)."""
+    returns the i-th batch of n uniforms.  loss: 'variance' (relative second
+    moment E[F^2]/E[F]^2) or 'kl' (KL divergence of the sampling density from
+    the integrand), both on weights capped at the batch's `clip` quantile.
+    Returns the map and the loss history."""
     m = WarpMap(ndim, nbins, device=device)
     opt = torch.optim.Adam(m.parameters(), lr=lr)
     hist = []
@@ -79,14 +92,14 @@ def train(fn, ndim, uniforms, iters=200, batch=1 << 14, nbins=32, lr=0.05, devic
         # the weights are heavy-tailed: the training loss caps them at the
         # batch's `clip` quantile (the estimates always use the raw weights)
         cap = torch.quantile(F.detach(), clip) if clip < 1.0 else None
-        loss = relative_second_moment(torch.minimum(F, cap) if cap is not None else F)
+        value = LOSSES[loss](torch.minimum(F, cap) if cap is not None else F)
         opt.zero_grad()
-        loss.backward()
+        value.backward()
         torch.nn.utils.clip_grad_norm_(m.parameters(), 1.0)
         opt.step()
-        hist.append(float(loss.detach()))
+        hist.append(float(value.detach()))
         if log and (it % max(1, iters // 10) == 0 or it == iters - 1):
-            log(f"iter {it} relative second moment {hist[-1]:.4g}")
+            log(f"iter {it} {loss} loss {hist[-1]:.4g}")
     return m, hist
 
 

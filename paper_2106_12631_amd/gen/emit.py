@@ -699,7 +699,7 @@ GRAD_PROCESSES = ('eemumu', 'ggtt', 'ggttg')
 # 2500 moves leave 4.5k recomputed flops per helicity, 20000 leave 3.5k)
 OPT_ITERS = 20000
 # amplitude terms between two scheduling fences (see fence() in helas.h)
-FENCE_EVERY = 4
+FENCE_EVERY = int(os.environ.get('MG_FENCE_EVERY', 4))
 # reverse-sweep steps between two fences in the adjoint code
 ADJ_FENCE_EVERY = int(os.environ.get('MG_ADJ_FENCE_EVERY', 4))
 
