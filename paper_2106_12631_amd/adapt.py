@@ -13,11 +13,27 @@ respect to the map's parameters needs df/dx, which the gradient kernel
 (mg_adjoint, the backward pass of MEWeight) provides.  E[F] is the same
 integral for every map, so the adapted sampler stays unbiased.
 
-The map is separable: per uniform, a monotone piecewise-linear warp of
-(0, 1) with nbins equal input bins whose output widths are softmax(logits)
-(a VEGAS-like grid trained by gradient descent instead of by histogram
-refinement).  It is elementwise torch arithmetic on the device; the matrix
-elements and their gradients come from the library's kernels.
+Without cuts a process with a final-state gluon has an infrared-divergent
+cross section (soft and beam-collinear gluons): E[F] grows with the sample
+and no map gives a finite variance.  The adaptation therefore takes an
+optional generator-level cut, pT > ptmin for chosen final-state particles,
+applied to the RAMBO momenta of each point (the integrand is f times the
+cut's indicator; the indicator is piecewise constant and carries no
+gradient).
+
+Two maps:
+  WarpMap       separable: per uniform, a monotone piecewise-linear warp of
+                (0, 1) with nbins equal input bins whose output widths are
+                softmax(logits) (a VEGAS-like grid trained by gradient
+                descent instead of by histogram refinement);
+  CouplingFlow  non-separable: a stack of piecewise-linear coupling layers
+                (the normalising-flow construction of neural importance
+                sampling: each layer warps half of the uniforms with bin
+                widths that a small network computes from the other half),
+                able to follow the correlations that RAMBO's boost puts
+                between the uniforms and the physical angles and energies.
+Both are torch arithmetic on the device; the matrix elements and their
+gradients come from the library's kernels.
 """
 import math
 
@@ -27,15 +43,17 @@ import torch
 class WarpMap(torch.nn.Module):
     """Per-dimension monotone piecewise-linear map of (0, 1) onto itself."""
 
-    def __init__(self, ndim, nbins=32, device=None, dtype=torch.float64):
+    def __init__(self, ndim, nbins=32, device=None, dtype=torch.float64, floor=0.0):
         super().__init__()
-        self.ndim, self.nbins = ndim, nbins
+        self.ndim, self.nbins, self.floor = ndim, nbins, floor
         self.logits = torch.nn.Parameter(torch.zeros(ndim, nbins, dtype=dtype, device=device))
 
     def forward(self, u):
         """x = g(u) and the Jacobian |dg/du| per event; u: (N, ndim) in (0, 1)."""
         K = self.nbins
-        w = torch.softmax(self.logits, dim=-1)              # output bin widths (ndim, K)
+        # output bin widths (ndim, K); `floor` mixes in the uniform map so that
+        # no bin is compressed below floor / K (bounds the weights' growth)
+        w = (1.0 - self.floor) * torch.softmax(self.logits, dim=-1) + self.floor / K
         left = torch.cumsum(w, dim=-1) - w                   # output left edges
         t = u * K
         k = t.detach().floor().clamp(0, K - 1).long()        # input bin per (event, dim)
@@ -47,6 +65,86 @@ class WarpMap(torch.nn.Module):
         x = x.clamp(tiny, 1.0 - tiny)
         jac = (K * wk).prod(dim=-1)
         return x, jac
+
+
+def _pwl(u, w):
+    """Monotone piecewise-linear map of (0, 1) with equal input bins and
+    output bin widths w (..., K), summing to 1: x and dx/du per entry."""
+    K = w.shape[-1]
+    t = u * K
+    k = t.detach().floor().clamp(0, K - 1).long().unsqueeze(-1)
+    left = torch.cumsum(w, dim=-1) - w
+    wk = torch.gather(w, -1, k).squeeze(-1)
+    x = torch.gather(left, -1, k).squeeze(-1) + (t - k.squeeze(-1)) * wk
+    return x, K * wk
+
+
+class CouplingFlow(torch.nn.Module):
+    """Stack of piecewise-linear coupling layers on (0, 1)^ndim.
+
+    Layer l splits the dimensions by bit (l // 2) of their index (the
+    complement on odd l, so every dimension is transformed and every pair of
+    dimensions is split by some layer); the transformed half is warped as in
+    _pwl with widths (1 - floor) softmax(net_l(identity half)) + floor / K.
+    The last linear layer of every network starts at zero: the flow starts
+    as the identity map."""
+
+    def __init__(self, ndim, nbins=32, layers=None, hidden=64, device=None,
+                 dtype=torch.float64, floor=0.0):
+        super().__init__()
+        self.ndim, self.nbins, self.floor = ndim, nbins, floor
+        nbits = max(1, (ndim - 1).bit_length())
+        layers = 2 * nbits if layers is None else layers
+        self.masks = []
+        self.nets = torch.nn.ModuleList()
+        for l in range(layers):
+            bit = (l // 2) % nbits
+            m = [((d >> bit) & 1) == (l % 2) for d in range(ndim)]
+            if all(m) or not any(m):
+                m = [d % 2 == l % 2 for d in range(ndim)]
+            ia = [d for d in range(ndim) if not m[d]]   # identity half
+            ib = [d for d in range(ndim) if m[d]]       # transformed half
+            self.masks.append((ia, ib))
+            net = torch.nn.Sequential(
+                torch.nn.Linear(len(ia), hidden, dtype=dtype, device=device), torch.nn.ReLU(),
+                torch.nn.Linear(hidden, hidden, dtype=dtype, device=device), torch.nn.ReLU(),
+                torch.nn.Linear(hidden, len(ib) * nbins, dtype=dtype, device=device))
+            torch.nn.init.zeros_(net[-1].weight)
+            torch.nn.init.zeros_(net[-1].bias)
+            self.nets.append(net)
+
+    def forward(self, u):
+        """x = g(u) and the Jacobian |dg/du| per event; u: (N, ndim) in (0, 1)."""
+        K = self.nbins
+        x = u
+        jac = torch.ones(u.shape[0], dtype=u.dtype, device=u.device)
+        for (ia, ib), net in zip(self.masks, self.nets):
+            logits = net(x[:, ia]).view(-1, len(ib), K)
+            w = (1.0 - self.floor) * torch.softmax(logits, dim=-1) + self.floor / K
+            xb, db = _pwl(x[:, ib], w)
+            x = x.index_copy(1, torch.tensor(ib, device=u.device), xb)
+            jac = jac * db.prod(dim=-1)
+        tiny = torch.finfo(u.dtype).eps
+        return x.clamp(tiny, 1.0 - tiny), jac
+
+
+MAPS = {'warp': WarpMap, 'coupling': CouplingFlow}
+
+
+def pt_cut(engine, particles, ptmin):
+    """Indicator of pT > ptmin for every particle in `particles` (0-based
+    indices in the process's particle order) at the RAMBO momenta of the
+    event-major uniforms r: a function r -> (N,) float64 tensor of 0 / 1."""
+    particles = list(particles)
+
+    def mask(r):
+        n = r.shape[0]
+        with torch.no_grad():
+            mom, _ = engine.rambo(engine.events_rnd(r.detach()), n)
+            p = engine.mom_events(mom, n)[:, particles]
+            pt = torch.hypot(p[..., 1], p[..., 2])
+            return (pt > ptmin).all(dim=-1).to(r.dtype)
+    return mask
 
 
 def relative_second_moment(F):
@@ -62,7 +160,15 @@ def kl_divergence(F):
     return (r * torch.log(r.clamp_min(1e-300))).mean()
 
 
-LOSSES = {'variance': relative_second_moment, 'kl': kl_divergence}
+def log_variance(F):
+    """Variance of log F over the points with F > 0 (cut points carry no
+    information on log F): zero at the optimum like the relative variance,
+    far less sensitive to the rare large weights of a heavy-tailed sample."""
+    lf = torch.log(F[F > 0])
+    return ((lf - lf.mean()) ** 2).mean()
+
+
+LOSSES = {'variance': relative_second_moment, 'kl': kl_divergence, 'logvar': log_variance}
 
 
 def estimate(F):
@@ -74,14 +180,16 @@ def estimate(F):
 
 
 def train(fn, ndim, uniforms, iters=200, batch=1 << 14, nbins=32, lr=0.05, device=None,
-          log=None, clip=0.995, loss='variance'):
+          log=None, clip=0.995, loss='variance', floor=0.0, flow='warp'):
     """Train a WarpMap for the integrand fn (a differentiable torch function
     of (N, ndim) points in (0, 1) returning (N,) weights); uniforms(i, n)
     returns the i-th batch of n uniforms.  loss: 'variance' (relative second
-    moment E[F^2]/E[F]^2) or 'kl' (KL divergence of the sampling density from
-    the integrand), both on weights capped at the batch's `clip` quantile.
+    moment E[F^2]/E[F]^2), 'kl' (KL divergence of the sampling density from
+    the integrand) or 'logvar' (variance of log F), each on weights capped at
+    the batch's `clip` quantile; floor: see WarpMap; flow: 'warp'
+    (WarpMap) or 'coupling' (CouplingFlow).
     Returns the map and the loss history."""
-    m = WarpMap(ndim, nbins, device=device)
+    m = MAPS[flow](ndim, nbins, device=device, floor=floor)
     opt = torch.optim.Adam(m.parameters(), lr=lr)
     hist = []
     for it in range(iters):
@@ -104,22 +212,25 @@ def train(fn, ndim, uniforms, iters=200, batch=1 << 14, nbins=32, lr=0.05, devic
 
 
 def adapt_process(engine, seed=4, iters=200, batch=1 << 14, nbins=32, lr=0.05, eval_batch=1 << 18,
-                  log=None):
+                  log=None, cut=None, clip=0.995, loss='variance', floor=0.0, flow='warp'):
     """Adapt the uniforms of engine's process and compare with flat sampling.
 
-    Training batches use Philox(seed) event ranges [i batch, (i+1) batch);
-    the two evaluations use disjoint ranges of Philox(seed + 1).  Returns a
-    dict with both estimates of sum-of-weights (w |M|^2 means), their errors,
-    relative variances and the variance reduction."""
+    cut: None or a function r -> (N,) indicator (see pt_cut) multiplying
+    the integrand.  Training batches use Philox(seed) event ranges
+    [i batch, (i+1) batch); the two evaluations use disjoint ranges of
+    Philox(seed + 1).  Returns a dict with both estimates of <w |M|^2 cut>,
+    their errors, relative variances and the variance reduction."""
     nr = engine.layout.nrnd
 
     def uniforms(i, n, s=seed):
         return engine.rnd_events(engine.rng(s, n, offset=i * n), n)
 
     def fn(x):
-        return engine.event_weight(x)
+        f = engine.event_weight(x)
+        return f if cut is None else f * cut(x)
 
-    m, hist = train(fn, nr, uniforms, iters, batch, nbins, lr, device=engine.device, log=log)
+    m, hist = train(fn, nr, uniforms, iters, batch, nbins, lr, device=engine.device, log=log,
+                    clip=clip, loss=loss, floor=floor, flow=flow)
     with torch.no_grad():
         u = uniforms(0, eval_batch, seed + 1)
         flat = fn(u)

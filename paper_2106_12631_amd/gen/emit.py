@@ -333,7 +333,7 @@ def _ext_code(n, name, npar):
     return f"cx<T> {name}[4]; {fn[0]}<T>({p}, {mass}, {hel}, {fn[1]}, {name});", FLOPS[routine]
 
 
-def emit_body(pd, coefs, order, bils, need, budget):
+def emit_body(pd, coefs, order, bils, need, budget, fence_every=4):
     """Straight-line body of jamps() for one register budget (in live
     wavefunctions).  Wavefunctions are computed on first use; when the
     budget is full the live one whose next use is farthest is dropped
@@ -417,7 +417,7 @@ def emit_body(pd, coefs, order, bils, need, budget):
         d, cf = pd.diagrams[k], coefs[k]
         nd = need(k)
         pin = {n.idx for n in nd}
-        if pos % FENCE_EVERY == 0:
+        if pos % fence_every == 0:
             L.append("  fence<UNI>(p);")
         names = [ensure(n, pos, pin) for n in nd]
         cl, cr = FFV[(d.fin.flav, d.vec.flav)]
@@ -698,10 +698,19 @@ GRAD_PROCESSES = ('eemumu', 'ggtt', 'ggttg')
 # local-search moves over the diagram order (gg -> t t~ g g at FP64 budget 16:
 # 2500 moves leave 4.5k recomputed flops per helicity, 20000 leave 3.5k)
 OPT_ITERS = 20000
-# amplitude terms between two scheduling fences (see fence() in helas.h)
-FENCE_EVERY = int(os.environ.get('MG_FENCE_EVERY', 4))
+# amplitude terms between two scheduling fences per precision (gg -> t t~ g g:
+# without fences FP64 halves its throughput; between 2 and 8 it moves by
+# under 1 %; FP32 one helicity per lane gains 4 % from 4 to 8 and loses 30 %
+# at 16; the mixed kernel gains 1 % from 4 to 12)
+FENCE = {'f64': 4, 'f32': 8, 'f32m': 12, 'a64': 4, 'a32': 4}
+
+
 # reverse-sweep steps between two fences in the adjoint code
 ADJ_FENCE_EVERY = int(os.environ.get('MG_ADJ_FENCE_EVERY', 4))
+
+
+def _fence(prec):
+    return int(os.environ.get(f'MG_FENCE_{prec.upper()}', FENCE[prec]))
 
 
 def _optimised_order(args):
@@ -769,7 +778,8 @@ def generate(name, orders=None):
     for prec, T, Rt, Ct in variants:
         budget = _budget(prec)
         order = orders[(name, budget)]
-        body, algo, execd, peak, rec = emit_body(pd, coefs, order, bils, need, budget)
+        body, algo, execd, peak, rec = emit_body(pd, coefs, order, bils, need, budget,
+                                                 fence_every=_fence(prec))
         stats[prec] = dict(flops_amp_per_hel=algo, flops_executed_per_hel=execd,
                            peak_live_wavefunctions=peak, recomputed=rec)
         jparam = f"cx<{T}> (&J)[{ncol}]"
@@ -813,7 +823,8 @@ def generate(name, orders=None):
         for prec, T, Ct in (('a64', 'double', 'double'), ('a32', 'float', 'float')):
             budget = _budget(prec)
             order = orders[(name, budget)]
-            fwd, algo, execd, peak, rec = emit_body(pd, coefs, order, bils, need, budget)
+            fwd, algo, execd, peak, rec = emit_body(pd, coefs, order, bils, need, budget,
+                                                    fence_every=_fence(prec))
             rev, rexec = emit_adjoint_body(pd, coefs, order, bils, need, budget)
             stats[prec] = dict(flops_forward_executed_per_hel=execd, flops_reverse_executed_per_hel=rexec)
             A.append(f"// reverse mode: returns the colour-summed |M|^2 of helicity hcode and adds")
