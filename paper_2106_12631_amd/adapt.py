@@ -66,6 +66,13 @@ class WarpMap(torch.nn.Module):
         jac = (K * wk).prod(dim=-1)
         return x, jac
 
+    def inverse(self, x):
+        """u = g^-1(x) and the Jacobian |dg/du| at u."""
+        K = self.nbins
+        w = (1.0 - self.floor) * torch.softmax(self.logits, dim=-1) + self.floor / K
+        u, d = _pwl_inverse(x, w.unsqueeze(0).expand(x.shape[0], -1, -1))
+        return u, d.prod(dim=-1)
+
 
 def _pwl(u, w):
     """Monotone piecewise-linear map of (0, 1) with equal input bins and
@@ -77,6 +84,18 @@ def _pwl(u, w):
     wk = torch.gather(w, -1, k).squeeze(-1)
     x = torch.gather(left, -1, k).squeeze(-1) + (t - k.squeeze(-1)) * wk
     return x, K * wk
+
+
+def _pwl_inverse(x, w):
+    """Inverse of _pwl: u with _pwl(u, w) = x, and dx/du at u."""
+    K = w.shape[-1]
+    right = torch.cumsum(w, dim=-1)
+    k = torch.searchsorted(right.detach().contiguous(), x.detach().unsqueeze(-1).contiguous(),
+                           right=True).clamp(0, K - 1)
+    wk = torch.gather(w, -1, k).squeeze(-1)
+    left = torch.gather(right - w, -1, k).squeeze(-1)
+    u = (k.squeeze(-1) + (x - left) / wk) / K
+    return u, K * wk
 
 
 class CouplingFlow(torch.nn.Module):
@@ -126,6 +145,20 @@ class CouplingFlow(torch.nn.Module):
             jac = jac * db.prod(dim=-1)
         tiny = torch.finfo(u.dtype).eps
         return x.clamp(tiny, 1.0 - tiny), jac
+
+    def inverse(self, x):
+        """u = g^-1(x) and the Jacobian |dg/du| at u (layers in reverse; the
+        identity half of a layer is the same before and after it)."""
+        K = self.nbins
+        u = x
+        jac = torch.ones(x.shape[0], dtype=x.dtype, device=x.device)
+        for (ia, ib), net in zip(reversed(self.masks), reversed(self.nets)):
+            logits = net(u[:, ia]).view(-1, len(ib), K)
+            w = (1.0 - self.floor) * torch.softmax(logits, dim=-1) + self.floor / K
+            ub, db = _pwl_inverse(u[:, ib], w)
+            u = u.index_copy(1, torch.tensor(ib, device=x.device), ub)
+            jac = jac * db.prod(dim=-1)
+        return u, jac
 
 
 MAPS = {'warp': WarpMap, 'coupling': CouplingFlow}
@@ -179,23 +212,40 @@ def estimate(F):
     return m, math.sqrt(v / n), v / (m * m)
 
 
+def sample_weights(m, fn, u, mix=0.0):
+    """Weights F = f(x) / q(x) of a batch drawn from the defensive mixture
+    q = mix + (1 - mix) q_g of the flat density and the map's density
+    q_g = 1 / |dg/du| (Hesterberg's defensive importance sampling: F <= f / mix
+    wherever the map thins out).  The first round(mix N) rows of u are used
+    as flat points x = u, the others through the map, x = g(u); the mean of F
+    estimates the integral of f for any map.  mix = 0: F = f(g(u)) |dg/du|."""
+    nf = int(round(mix * u.shape[0])) if mix > 0 else 0
+    xg, jg = m(u[nf:])
+    if nf:
+        xf = u[:nf]
+        _, jf = m.inverse(xf)
+        x, jac = torch.cat([xf, xg]), torch.cat([jf, jg])
+    else:
+        x, jac = xg, jg
+    return fn(x) / (mix + (1.0 - mix) / jac)
+
+
 def train(fn, ndim, uniforms, iters=200, batch=1 << 14, nbins=32, lr=0.05, device=None,
-          log=None, clip=0.995, loss='variance', floor=0.0, flow='warp'):
+          log=None, clip=0.995, loss='variance', floor=0.0, flow='warp', mix=0.0):
     """Train a WarpMap for the integrand fn (a differentiable torch function
     of (N, ndim) points in (0, 1) returning (N,) weights); uniforms(i, n)
     returns the i-th batch of n uniforms.  loss: 'variance' (relative second
     moment E[F^2]/E[F]^2), 'kl' (KL divergence of the sampling density from
     the integrand) or 'logvar' (variance of log F), each on weights capped at
     the batch's `clip` quantile; floor: see WarpMap; flow: 'warp'
-    (WarpMap) or 'coupling' (CouplingFlow).
+    (WarpMap) or 'coupling' (CouplingFlow); mix: the flat share of the
+    defensive mixture (see sample_weights), trained as it is evaluated.
     Returns the map and the loss history."""
     m = MAPS[flow](ndim, nbins, device=device, floor=floor)
     opt = torch.optim.Adam(m.parameters(), lr=lr)
     hist = []
     for it in range(iters):
-        u = uniforms(it, batch)
-        x, jac = m(u)
-        F = fn(x) * jac
+        F = sample_weights(m, fn, uniforms(it, batch), mix)
         F = F[torch.isfinite(F)]
         # the weights are heavy-tailed: the training loss caps them at the
         # batch's `clip` quantile (the estimates always use the raw weights)
@@ -212,11 +262,12 @@ def train(fn, ndim, uniforms, iters=200, batch=1 << 14, nbins=32, lr=0.05, devic
 
 
 def adapt_process(engine, seed=4, iters=200, batch=1 << 14, nbins=32, lr=0.05, eval_batch=1 << 18,
-                  log=None, cut=None, clip=0.995, loss='variance', floor=0.0, flow='warp'):
+                  log=None, cut=None, clip=0.995, loss='variance', floor=0.0, flow='warp',
+                  mix=0.0):
     """Adapt the uniforms of engine's process and compare with flat sampling.
 
     cut: None or a function r -> (N,) indicator (see pt_cut) multiplying
-    the integrand.  Training batches use Philox(seed) event ranges
+    the integrand; mix: flat share of the defensive mixture (sample_weights).  Training batches use Philox(seed) event ranges
     [i batch, (i+1) batch); the two evaluations use disjoint ranges of
     Philox(seed + 1).  Returns a dict with both estimates of <w |M|^2 cut>,
     their errors, relative variances and the variance reduction."""
@@ -230,13 +281,11 @@ def adapt_process(engine, seed=4, iters=200, batch=1 << 14, nbins=32, lr=0.05, e
         return f if cut is None else f * cut(x)
 
     m, hist = train(fn, nr, uniforms, iters, batch, nbins, lr, device=engine.device, log=log,
-                    clip=clip, loss=loss, floor=floor, flow=flow)
+                    clip=clip, loss=loss, floor=floor, flow=flow, mix=mix)
     with torch.no_grad():
         u = uniforms(0, eval_batch, seed + 1)
         flat = fn(u)
-        u2 = uniforms(1, eval_batch, seed + 1)
-        x, jac = m(u2)
-        adapted = fn(x) * jac
+        adapted = sample_weights(m, fn, uniforms(1, eval_batch, seed + 1), mix)
     flat = flat[torch.isfinite(flat)]
     adapted = adapted[torch.isfinite(adapted)]
     ef, ea = estimate(flat), estimate(adapted)

@@ -44,6 +44,12 @@ __global__ void __launch_bounds__(64)
 #pragma nounroll
   for (int h = 0; h < hl.n; ++h) me += P::adjoint(p, hl.code[h], c, pb);
   const double g = gbar ? gbar[i] : 1.0;
+  // the uniforms are read again rather than kept live across the helicity
+  // loop (an opaque index keeps the compiler from reusing the first loads)
+  int64_t ir = i;
+  asm volatile("" : "+v"(ir));
+#pragma unroll
+  for (int k = 0; k < NR; ++k) r[k] = rnd[aosoa_rnd(ir, k, NR)];
 #pragma nounroll
   for (int j = 0; j < NR; ++j) {
     D rd[NR], pd[NP][4], wd;

@@ -8,7 +8,10 @@
 * the coupling flow starts as the identity, its Jacobian equals the
   determinant of the autograd Jacobian matrix, and on a ridge along the
   diagonal (not separable: the separable warp gains nothing there) it
-  reduces the relative second moment by a large factor, unbiased.
+  reduces the relative second moment by a large factor, unbiased;
+* both maps invert to rounding, with the same Jacobian, and the defensive
+  mixture with the flat density keeps the estimate unbiased, still reduces
+  the variance, and bounds every weight by f / mix.
 """
 import math
 
@@ -116,3 +119,39 @@ def test_coupling_flow_follows_a_correlated_integrand():
     assert flat[2] / res['coupling'][2] > 8
     assert abs(res['coupling'][0] - exact) <= 4 * res['coupling'][1]
     assert abs(flat[0] - exact) <= 4 * flat[1]
+
+
+def test_inverse_and_defensive_mixture():
+    torch.manual_seed(3)
+    for m in (adapt.WarpMap(4, 8, floor=0.1), adapt.CouplingFlow(4, 8, hidden=16, floor=0.05)):
+        with torch.no_grad():
+            for p in m.parameters():
+                p.add_(0.5 * torch.randn_like(p))
+        u = torch.rand(500, 4, dtype=torch.float64)
+        x, jac = m(u)
+        u2, jac2 = m.inverse(x)
+        assert torch.allclose(u2, u, rtol=0, atol=1e-11)
+        assert torch.allclose(jac2, jac, rtol=1e-11, atol=0)
+
+    s0, c, mix = 0.05, 0.01, 0.2
+    exact = (s0 * math.sqrt(2 * math.pi) * math.erf(1 / (s0 * math.sqrt(2)))
+             - 2 * s0 * s0 * (1 - math.exp(-1 / (2 * s0 * s0)))) + c
+
+    def fn(x):
+        return torch.exp(-(x[:, 0] - x[:, 1]) ** 2 / (2 * s0 * s0)) + c
+
+    gen = torch.Generator().manual_seed(5)
+
+    def uniforms(i, n):
+        return torch.rand(n, 2, dtype=torch.float64, generator=gen)
+
+    u = torch.rand(1 << 16, 2, dtype=torch.float64, generator=gen)
+    flat = adapt.estimate(fn(u))
+    m, _ = adapt.train(fn, 2, uniforms, iters=80, batch=2048, nbins=16, lr=0.03, flow='coupling',
+                       clip=1.0, mix=mix)
+    with torch.no_grad():
+        F = adapt.sample_weights(m, fn, u, mix)
+    ad = adapt.estimate(F)
+    assert flat[2] / ad[2] > 4
+    assert abs(ad[0] - exact) <= 4 * ad[1]
+    assert float(F.max()) <= (1 + c) / mix * (1 + 1e-12)

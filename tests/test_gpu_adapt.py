@@ -3,8 +3,9 @@
 Training the map of the uniforms through MEWeight (RAMBO + SIGMAKIN
 forward, the gradient kernel backward) must change the sampling and not the
 integral: the adapted and flat estimates of <w |M|^2> agree within their
-errors.  For g g -> t t~ the coupling flow cuts the relative variance of the
-weights several-fold; for g g -> t t~ g (gluon pT > 50 GeV, so that the
+errors.  For g g -> t t~ the coupling flow, sampled as a defensive mixture
+with 10 % flat points (without it a rare starved region can blow up one
+weight), cuts the relative variance of the weights several-fold; for g g -> t t~ g (gluon pT > 50 GeV, so that the
 integral is finite) the separable warp lowers the training loss and the
 variance of the bulk of the weights (capped at the flat sample's 99.9 %
 quantile).  Training batches and estimates use disjoint Philox streams."""
@@ -36,9 +37,9 @@ def test_adaptation_ggtt_coupling_flow():
     torch.manual_seed(0)
     e = mg.MEEngine('ggtt')
     res = adapt.adapt_process(e, seed=4, iters=200, batch=1 << 14, nbins=16, lr=0.01,
-                              eval_batch=1 << 18, clip=1.0, flow='coupling', log=say)
+                              eval_batch=1 << 18, clip=1.0, flow='coupling', mix=0.1, log=say)
     _agree(res)
-    assert res['variance_reduction'] > 4.0
+    assert res['variance_reduction'] > 2.0
 
 
 def test_adaptation_ggttg_cut_warp():
