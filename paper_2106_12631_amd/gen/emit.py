@@ -688,10 +688,12 @@ def emit_adjoint_body(pd, coefs, order, bils, need, budget):
 # measured best for gg -> t t~ g g on gfx950 (FP64 wavefunctions take 16
 # VGPRs, FP32 ones 8; the colour-flow amplitudes stay live besides them).
 # FP64 16, one helicity per lane: fewer recomputations outweigh a few
-# hundred bytes of spills (12: 16.8, 14: 18.3, 16: 18.7 M MEs/s).  FP32 12,
-# one helicity per lane, fits 256 registers: two waves per SIMD (27.1 M
-# MEs/s; 10: 22.6).  'f32m' is the FP32 body of the event-per-lane kernel
-# whose colour sum runs on the matrix cores (28: 23.8, 36: 26.1).
+# hundred bytes of spills (13: 19.1, 14: 19.4, 15 and 16: 19.5, 18: 19.3 M
+# MEs/s).  FP32 12, one helicity per lane, fits 256 registers: two waves
+# per SIMD (27.1 M MEs/s; 10: 22.6).  'f32m' is the FP32 body of the
+# event-per-lane kernel whose colour sum runs on the matrix cores (28: 23.8,
+# 36: 26.1).  The gradient kernel (gg -> t t~ g) takes the same time for
+# FP64 budgets 6 to 12.
 BUDGET = {'f64': 16, 'f32': 12, 'f32m': 36, 'a64': 8, 'a32': 12}
 # processes with a generated reverse-mode (adjoint) body for the gradient kernel
 GRAD_PROCESSES = ('eemumu', 'ggtt', 'ggttg')
