@@ -47,6 +47,8 @@ def kernel_source_hash(proc):
         with open(os.path.join(csrc, n), 'rb') as fh:
             h.update(fh.read())
     h.update(' '.join(a for a in _build.FLAGS if not a.startswith('/')).encode())
+    for n in names:
+        h.update(' '.join(_build.SOURCE_FLAGS.get(n, ())).encode())
     return h.hexdigest()[:16]
 
 

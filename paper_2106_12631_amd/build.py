@@ -24,6 +24,15 @@ FLAGS = [
     '-I', CSRC, '-I', INCLUDE,
 ]
 
+# Flags of single sources.  The helicity-per-lane mixed kernel calls its
+# matrix-core colour sum out of line; with the MFMA results in VGPRs and the
+# callee's saved registers on the stack instead of in AGPRs it needs no AGPRs
+# and runs two waves per SIMD.
+SOURCE_FLAGS = {
+    'sigmakin_ggttgg_mixed.hip': ['-mllvm', '-amdgpu-mfma-vgpr-form',
+                                  '-mllvm', '-amdgpu-spill-vgpr-to-agpr=0'],
+}
+
 
 def sources():
     return sorted(f for f in os.listdir(CSRC) if f.endswith('.hip'))
@@ -40,7 +49,8 @@ def build(force=True, verbose=True, extra_flags=(), output=None):
     for src in sources():
         obj = os.path.join(BUILD, src.replace('.hip', '.o'))
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, *extra_flags, '-c', os.path.join(CSRC, src), '-o', obj]
+        cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, ()), *extra_flags, '-c',
+               os.path.join(CSRC, src), '-o', obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
     for src, p in procs:

@@ -121,19 +121,29 @@ struct ColourMfmaF32 {
 
   // returns sum_ij C_ij Re(conj(J_i) J_j) (numerators of C) for this lane's event
   __device__ __forceinline__ float sum(const cx<float> (&J)[NCOL], int lane) {
+    return sum_parts([&](int part, int k) { return part ? J[k].i : J[k].r; },
+                     [&](int kb) { return a[kb]; }, lane);
+  }
+
+  // the same with the amplitudes read through get(part, k) (part 0: real,
+  // 1: imaginary), one part at a time, and the A operand of K block kb
+  // through aop(kb) (e.g. from a table written by save())
+  template <class Get, class AOp>
+  __device__ __forceinline__ float sum_parts(Get get, AOp aop, int lane) {
     float part_lo = 0.f, part_hi = 0.f;
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
       float x[NCOL];
 #pragma unroll
-      for (int k = 0; k < NCOL; ++k) x[k] = part ? J[k].i : J[k].r;
+      for (int k = 0; k < NCOL; ++k) x[k] = get(part, k);
       floatx16 dlo = {0}, dhi = {0};
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
         float blo, bhi;
         swap_halves(x[2 * kb], 2 * kb + 1 < NCOL ? x[2 * kb + 1] : 0.f, blo, bhi);
-        dlo = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb], blo, dlo, 0, 0, 0);
-        dhi = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kb], bhi, dhi, 0, 0, 0);
+        const float ak = aop(kb);
+        dlo = __builtin_amdgcn_mfma_f32_32x32x2f32(ak, blo, dlo, 0, 0, 0);
+        dhi = __builtin_amdgcn_mfma_f32_32x32x2f32(ak, bhi, dhi, 0, 0, 0);
       }
       tile_dots<NCOL>(dlo, dhi, x, part_lo, part_hi);
     }
@@ -181,27 +191,31 @@ struct ColourMfmaBf16 {
     }
   }
 
+  // term s (0: hi, 1: mid, 2: lo) of the exact three-term split of v by
+  // truncation, its bits in the upper half of a 32-bit word; computed where
+  // a K block needs it rather than kept for all colours
+  __device__ static __forceinline__ unsigned split(float v, int s) {
+    const unsigned hi = __float_as_uint(v) & 0xFFFF0000u;
+    if (s == 0) return hi;
+    const float r1 = v - __uint_as_float(hi);
+    const unsigned mid = __float_as_uint(r1) & 0xFFFF0000u;
+    if (s == 1) return mid;
+    return __float_as_uint(r1 - __uint_as_float(mid));
+  }
+
   __device__ __forceinline__ float sum(const cx<float> (&J)[NCOL], int lane) {
+    return sum_parts([&](int part, int k) { return part ? J[k].i : J[k].r; },
+                     [&](int kb) { return a[kb]; }, lane);
+  }
+
+  template <class Get, class AOp>
+  __device__ __forceinline__ float sum_parts(Get get, AOp aop, int lane) {
     float part_lo = 0.f, part_hi = 0.f;
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
       float x[NCOL];
 #pragma unroll
-      for (int k = 0; k < NCOL; ++k) x[k] = part ? J[k].i : J[k].r;
-      // exact three-term split by truncation; each term's bits in the upper
-      // half of a 32-bit word
-      unsigned sp[3][8 * G];
-#pragma unroll
-      for (int k = 0; k < 8 * G; ++k) {
-        const float v = k < NCOL ? x[k] : 0.f;
-        const unsigned hi = __float_as_uint(v) & 0xFFFF0000u;
-        const float r1 = v - __uint_as_float(hi);
-        const unsigned mid = __float_as_uint(r1) & 0xFFFF0000u;
-        const float r2 = r1 - __uint_as_float(mid);
-        sp[0][k] = hi;
-        sp[1][k] = mid;
-        sp[2][k] = __float_as_uint(r2);
-      }
+      for (int k = 0; k < NCOL; ++k) x[k] = get(part, k);
       floatx16 dlo = {0}, dhi = {0};
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
@@ -212,17 +226,20 @@ struct ColourMfmaBf16 {
 #pragma unroll
           for (int t = 0; t < 2; ++t) {
             const int c = 2 * kb + t, s = c / G, g = c % G;
-            w[t] = c < NCH ? (sp[s][8 * g + 2 * q] >> 16) | (sp[s][8 * g + 2 * q + 1] & 0xFFFF0000u)
+            const int k0 = 8 * g + 2 * q, k1 = k0 + 1;
+            w[t] = c < NCH ? (split(k0 < NCOL ? x[k0] : 0.f, s) >> 16) |
+                                 (split(k1 < NCOL ? x[k1] : 0.f, s) & 0xFFFF0000u)
                            : 0u;
           }
           swap_halves(w[0], w[1], ulo[q], uhi[q]);
         }
         const uintx4 vlo = {ulo[0], ulo[1], ulo[2], ulo[3]};
         const uintx4 vhi = {uhi[0], uhi[1], uhi[2], uhi[3]};
-        dlo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kb], __builtin_bit_cast(bf16x8, vlo), dlo,
-                                                      0, 0, 0);
-        dhi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[kb], __builtin_bit_cast(bf16x8, vhi), dhi,
-                                                      0, 0, 0);
+        const bf16x8 ak = aop(kb);
+        dlo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ak, __builtin_bit_cast(bf16x8, vlo), dlo, 0,
+                                                      0, 0);
+        dhi = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ak, __builtin_bit_cast(bf16x8, vhi), dhi, 0,
+                                                      0, 0);
       }
       tile_dots<NCOL>(dlo, dhi, x, part_lo, part_hi);
     }

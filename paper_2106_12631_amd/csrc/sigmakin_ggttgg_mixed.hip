@@ -1,5 +1,7 @@
 // SIGMAKIN for ggttgg, mixed precision: FP32 colour-flow amplitudes and the
-// colour sum on the matrix cores (kernels of sigmakin_impl.h).
+// colour sum on the matrix cores (kernels of sigmakin_impl.h): one helicity
+// per lane with the FP32 body of the helicity-per-lane FP32 kernel when all
+// 64 helicities are kept, else event per lane with its own body.
 #include "sigmakin_impl.h"
 
 namespace mg {
@@ -21,14 +23,24 @@ struct P_ggttgg {
   }
 };
 
+struct P_ggttgg_hpl : P_ggttgg {
+  template <typename T, bool UNI = false>
+  __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
+                                               const Couplings<float>& c, cx<float> (&J)[NCOL]) {
+    gen_ggttgg::jamps<float, UNI>(p, h, c, J);
+  }
+};
+
 int launch_sigmakin_ggttgg_mfma_f32(const MeArgs& a, const double* mom, int64_t nevt, double* me,
                                 const double* wgt, double* evtw, hipStream_t s) {
-  return sigmakin_mixed_launch<P_ggttgg, ColourMfmaF32>(a, mom, nevt, me, wgt, evtw, s);
+  return sigmakin_mixed_hpl_launch<P_ggttgg, P_ggttgg_hpl, ColourMfmaF32>(a, mom, nevt, me, wgt,
+                                                                          evtw, s);
 }
 
 int launch_sigmakin_ggttgg_mfma_bf16(const MeArgs& a, const double* mom, int64_t nevt, double* me,
                                  const double* wgt, double* evtw, hipStream_t s) {
-  return sigmakin_mixed_launch<P_ggttgg, ColourMfmaBf16>(a, mom, nevt, me, wgt, evtw, s);
+  return sigmakin_mixed_hpl_launch<P_ggttgg, P_ggttgg_hpl, ColourMfmaBf16>(a, mom, nevt, me, wgt,
+                                                                           evtw, s);
 }
 
 }  // namespace mg

@@ -7,7 +7,10 @@
 //                            helicities): wave-uniform momenta in scalar
 //                            registers, helicity sum by wave reduction;
 //   sigmakin_mixed_kernel    event per lane with the colour sum on the
-//                            matrix cores (colour_mfma.h).
+//                            matrix cores (colour_mfma.h);
+//   sigmakin_mixed_hpl_kernel  one event per wave, one helicity per lane,
+//                            the 64 helicities' amplitudes as the 64 columns
+//                            of the matrix-core colour sum.
 #pragma once
 #include "colour_mfma.h"
 #include "common.h"
@@ -158,6 +161,69 @@ __global__ void __launch_bounds__(64)
     if (me) me[i] = m;
     if (evtw) evtw[i] = m * wgt[i];
   }
+}
+
+// Matrix-core colour sum of one helicity per lane, kept out of line: with
+// the MFMA code inlined after the amplitudes the compiler spills about 1 KB
+// per lane of the amplitude code; behind a call the kernel keeps the
+// register allocation of the FP32 amplitude body and two waves per SIMD
+// (with MFMA results in VGPRs and the callee's saved registers on the stack
+// rather than in AGPRs: the flags of this kernel's source file).  The
+// amplitudes cross the call in LDS, jl[(2 k + part) * 64 + lane]: each lane
+// reads back only its own values, so no barrier is needed.
+typedef __attribute__((address_space(3))) float lds_float;
+
+template <template <int> class CS, int NCOL>
+__device__ __noinline__ float colour_sum_mfma_call(const lds_float* jl, const int* cnum,
+                                                   int lane) {
+  CS<NCOL> cs;
+  cs.init(cnum, lane);
+  return cs.sum_parts([&](int part, int k) { return jl[(2 * k + part) * 64 + lane]; },
+                      [&](int kb) { return cs.a[kb]; }, lane);
+}
+
+// Mixed precision with one helicity per lane: the 64 helicities of one event
+// are the 64 columns of the matrix-core colour sum (the same product as for
+// 64 events), whose per-lane results are summed over the wave in FP64.
+template <class P, template <int> class CS>
+__global__ void __launch_bounds__(64)
+    sigmakin_mixed_hpl_kernel(const double* __restrict__ mom, int64_t nevt,
+                              double* __restrict__ me, const double* __restrict__ wgt,
+                              double* __restrict__ evtw, Couplings<float> c, double inv_iden) {
+  static_assert((1 << P::NPAR) == 64, "one helicity per lane of a wave64");
+  const int64_t i = xcd_event(blockIdx.x, nevt);
+  const int lane = threadIdx.x;
+  double q[P::NPAR][4];
+  load_event<P>(mom, i, q);
+  cx<float> J[P::NCOL];
+  P::template jamps<float, true>(q, (unsigned)lane, c, J);
+  __shared__ float jl[2 * P::NCOL * 64];
+#pragma unroll
+  for (int k = 0; k < P::NCOL; ++k) {
+    jl[(2 * k) * 64 + lane] = J[k].r;
+    jl[(2 * k + 1) * 64 + lane] = J[k].i;
+  }
+  double v = (double)colour_sum_mfma_call<CS, P::NCOL>((const lds_float*)jl, P::cnum(), lane);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (lane == 0) {
+    const double m = v * (inv_iden / P::CDEN);
+    if (me) me[i] = m;
+    if (evtw) evtw[i] = m * wgt[i];
+  }
+}
+
+// helicity-per-lane mixed launch when every helicity is kept, else the
+// event-per-lane mixed kernel (PH: the traits of the helicity-per-lane body)
+template <class P, class PH, template <int> class CS>
+int sigmakin_mixed_hpl_launch(const MeArgs& a, const double* mom, int64_t nevt, double* me,
+                              const double* wgt, double* evtw, hipStream_t s) {
+  if (a.hel.n == (1 << P::NPAR) && nevt > 0 && nevt <= 0x7FFFFFFF) {
+    sigmakin_mixed_hpl_kernel<PH, CS><<<(unsigned)nevt, 64, 0, s>>>(mom, nevt, me, wgt, evtw,
+                                                                   a.c32, a.inv_iden);
+    return 0;
+  }
+  return sigmakin_mixed_launch<P, CS>(a, mom, nevt, me, wgt, evtw, s);
 }
 
 // helicity-per-lane launch when every helicity is kept, else the
