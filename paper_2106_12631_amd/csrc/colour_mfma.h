@@ -109,13 +109,24 @@ struct ColourMfmaF32 {
     for (int kb = 0; kb < KB; ++kb) a[kb] = tab[kb * 64 + lane];
   }
 
-  // cnum: the NCOL x NCOL integer numerators of C, row-major
+  // cnum: the NCOL x NCOL integer numerators of C, row-major.  Every lane
+  // loads an in-range entry and multiplies it by 0 where the tile is padding
+  // (a selected value would let the compiler move each load into a branch
+  // of its own), and all loads are issued before the first is used: one
+  // memory latency instead of one per load.
   __device__ __forceinline__ void init(const int* cnum, int lane) {
     const int m = lane & 31, kh = lane >> 5;
+    int v[KB];
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
       const int k = 2 * kb + kh;
-      a[kb] = (m < NCOL && k < NCOL) ? (float)cnum[m * NCOL + k] : 0.f;
+      v[kb] = cnum[(m < NCOL ? m : NCOL - 1) * NCOL + (k < NCOL ? k : NCOL - 1)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int k = 2 * kb + kh;
+      a[kb] = (float)v[kb] * ((m < NCOL && k < NCOL) ? 1.f : 0.f);
     }
   }
 
@@ -168,8 +179,20 @@ struct ColourMfmaBf16 {
     for (int kb = 0; kb < KB; ++kb) a[kb] = __builtin_bit_cast(bf16x8, tab[kb * 64 + lane]);
   }
 
+  // as ColourMfmaF32::init
   __device__ __forceinline__ void init(const int* cnum, int lane) {
     const int m = lane & 31, kh = lane >> 5;
+    int v[KB][8];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const int g = (2 * kb + kh) % G;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int col = 8 * g + j;
+        v[kb][j] = cnum[(m < NCOL ? m : NCOL - 1) * NCOL + (col < NCOL ? col : NCOL - 1)];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
       const int c = 2 * kb + kh, g = c % G;
@@ -180,9 +203,8 @@ struct ColourMfmaBf16 {
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           const int col = 8 * g + 2 * q + t;
-          h[t] = (m < NCOL && c < NCH && col < NCOL)
-                     ? bf16_exact_bits((float)cnum[m * NCOL + col])
-                     : (unsigned short)0;
+          h[t] = bf16_exact_bits((float)v[kb][2 * q + t] *
+                                 ((m < NCOL && c < NCH && col < NCOL) ? 1.f : 0.f));
         }
         u[q] = (unsigned)h[0] | ((unsigned)h[1] << 16);
       }
