@@ -167,8 +167,9 @@ PEAK_MFMA = {'bf16': 2.5e15, 'f32': 157.3e12}  # dense FLOP/s, MI355X
 
 
 def mfma_work(ncol, nhel, prec, proc, seconds, nevt):
-    """Matrix-core work of the colour sum as executed: per helicity and wave
-    of 64 events, 2 parts x K blocks x 2 tiles of 32x32 outputs."""
+    """Matrix-core work of the colour sum as executed: per 64 columns (64
+    events of one helicity, or the 64 helicities of one event), 2 parts x
+    K blocks x 2 tiles of 32x32 outputs."""
     bf16 = prec == 'mixed' and proc == 'ggttgg'
     if bf16:
         kb, k = (3 * ((ncol + 7) // 8) + 1) // 2, 16
@@ -305,7 +306,7 @@ def main():
         "config": {"workload": f"{args.process} {args.nevt} events seed {args.seed} "
                                f"sqrt(s)=1500 GeV (Philox + RAMBO + |M|^2)",
                    "process": args.process, "nevt": args.nevt, "seed": args.seed,
-                   "parallelism": "1 GPU, one event per lane"},
+                   "parallelism": "1 GPU, one event per wave, one helicity per lane"},
         "roofline": head["roofline"],
         "cpu_baseline": cpu,
         "variants": results,
