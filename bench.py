@@ -246,7 +246,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(events shard trivially across GPUs, see the design notes)", file=sys.stderr)
+              f"(events are independent: they would shard as one contiguous event range "
+              f"per GPU)", file=sys.stderr)
         sys.exit(2)
 
     cpu = None
