@@ -438,6 +438,27 @@ __device__ __forceinline__ cx<T> ffv_amp(const cx<T> F[4], const cx<T> V[4], con
   return times_i(mdot(J, V));
 }
 
+// Vector-like vertices (cL = cR = g: gluon, photon).  The bilinear without
+// the coupling, F gamma^mu G, and the amplitude with g applied once to the
+// result instead of to every component.
+template <typename T>
+__device__ __forceinline__ void ffv_bilinear_v(const cx<T> F[4], const cx<T> G[4], cx<T> J[4]) {
+  const cx<T> a00 = F[0] * G[2], a11 = F[1] * G[3], a01 = F[0] * G[3], a10 = F[1] * G[2];
+  const cx<T> b00 = F[2] * G[0], b11 = F[3] * G[1], b01 = F[2] * G[1], b10 = F[3] * G[0];
+  J[0] = (a00 + a11) + (b00 + b11);
+  J[1] = (a01 + a10) - (b01 + b10);
+  J[2] = times_i((a10 - a01) - (b10 - b01));
+  J[3] = (a00 - a11) - (b00 - b11);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> ffv_amp_v(const cx<T> F[4], const cx<T> V[4], const cx<T> G[4],
+                                           base_t<T> g) {
+  cx<T> J[4];
+  ffv_bilinear_v(F, G, J);
+  return g * times_i(mdot(J, V));
+}
+
 // vector current from F, G through a massless (photon, gluon) propagator:
 // (-i/K^2) i J^mu = J^mu / K^2
 template <typename T, typename R>
@@ -509,6 +530,50 @@ __device__ __forceinline__ void ffv_cur_fout(const cx<T> F[4], const cx<T> V[4],
   sbK_row(k, f2, f3, y0, y1);
   sK_row(k, f0, f1, y2, y3);
   const cx<T> d = -inv_den<T>(msq(K) - m * m, R(m * w));
+  out[0] = d * rmadd(mm, f0, -y0);
+  out[1] = d * rmadd(mm, f1, -y1);
+  out[2] = d * rmadd(mm, f2, -y2);
+  out[3] = d * rmadd(mm, f3, -y3);
+}
+
+// ffv_cur_fin and ffv_cur_fout for a vector-like vertex (cL = cR = g): the
+// coupling joins the propagator factor instead of every component
+template <typename T, typename R>
+__device__ __forceinline__ void ffv_cur_fin_v(const cx<T> V[4], const cx<T> G[4], base_t<T> g,
+                                              const R K[4], double m, double w, cx<T> out[4]) {
+  blk<T> s, sb;
+  slash_blocks(V, s, sb);
+  cx<T> f0, f1, f2, f3;
+  mcol(s, G[2], G[3], f0, f1);
+  mcol(sb, G[0], G[1], f2, f3);
+  T k[4];
+  to_T(K, k);
+  const T mm = (T)m;
+  cx<T> y0, y1, y2, y3;
+  sK_col(k, f2, f3, y0, y1);
+  sbK_col(k, f0, f1, y2, y3);
+  const cx<T> d = -g * inv_den<T>(msq(K) - m * m, R(m * w));
+  out[0] = d * rmadd(mm, f0, y0);
+  out[1] = d * rmadd(mm, f1, y1);
+  out[2] = d * rmadd(mm, f2, y2);
+  out[3] = d * rmadd(mm, f3, y3);
+}
+
+template <typename T, typename R>
+__device__ __forceinline__ void ffv_cur_fout_v(const cx<T> F[4], const cx<T> V[4], base_t<T> g,
+                                               const R K[4], double m, double w, cx<T> out[4]) {
+  blk<T> s, sb;
+  slash_blocks(V, s, sb);
+  cx<T> f0, f1, f2, f3;
+  mrow(sb, F[2], F[3], f0, f1);
+  mrow(s, F[0], F[1], f2, f3);
+  T k[4];
+  to_T(K, k);
+  const T mm = (T)m;
+  cx<T> y0, y1, y2, y3;
+  sbK_row(k, f2, f3, y0, y1);
+  sK_row(k, f0, f1, y2, y3);
+  const cx<T> d = -g * inv_den<T>(msq(K) - m * m, R(m * w));
   out[0] = d * rmadd(mm, f0, -y0);
   out[1] = d * rmadd(mm, f1, -y1);
   out[2] = d * rmadd(mm, f2, -y2);

@@ -25,6 +25,8 @@ FLOPS = {
     'vec_in': 22, 'vec_out': 22, 'ubar': 30, 'u': 30, 'v': 30, 'vbar': 30,
     'ffv_amp': 118, 'ffv_cur_v0': 104, 'ffv_cur_vm': 140,
     'ffv_cur_fin': 171, 'ffv_cur_fout': 171,
+    # vector-like vertices (cL = cR): the coupling applied once
+    'ffv_amp_v': 104, 'ffv_cur_fin_v': 165, 'ffv_cur_fout_v': 165,
     'vvv_cur': 187, 'vvvv_cur': 128,
     'ffv_bil': 88, 'amp_dot': 30,
     'jamp_acc': 2,
@@ -143,8 +145,11 @@ def _node_flops(n):
         return FLOPS[n.op[2]]
     if op == 'ffv_v':
         return FLOPS['ffv_cur_v0'] if BOSON_MASS[n.op[3]] is None else FLOPS['ffv_cur_vm']
-    return FLOPS[{'vvv': 'vvv_cur', 'vvvv': 'vvvv_cur', 'ffv_fout': 'ffv_cur_fout',
-                  'ffv_fin': 'ffv_cur_fin'}[op]]
+    if op in ('ffv_fout', 'ffv_fin'):
+        f, vec = (n.op[1], n.op[2]) if op == 'ffv_fout' else (n.op[2], n.op[1])
+        cl, cr = FFV[(f.flav, vec.flav)]
+        return FLOPS[f'ffv_cur_{op[4:]}' + ('_v' if cl == cr else '')]
+    return FLOPS[{'vvv': 'vvv_cur', 'vvvv': 'vvvv_cur'}[op]]
 
 
 def schedule_cost(order, need, budget):
@@ -296,6 +301,10 @@ def _node_code(n, name, dn, parts):
         f, vec = op[1], op[2]
         cl, cr = FFV[(f.flav, vec.flav)]
         m, wd = FERMION_MASS[f.flav]
+        if cl == cr:
+            return (f"cx<T> {name}[4]; {{ const R K[4] = {K}; "
+                    f"ffv_cur_fout_v<T>({dn[0]}, {dn[1]}, c.{cl}, K, c.{m}, c.{wd}, {name}); }}",
+                    FLOPS['ffv_cur_fout_v'])
         return (f"cx<T> {name}[4]; {{ const R K[4] = {K}; "
                 f"ffv_cur_fout<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{m}, c.{wd}, {name}); }}",
                 FLOPS['ffv_cur_fout'])
@@ -303,6 +312,10 @@ def _node_code(n, name, dn, parts):
         vec, f = op[1], op[2]
         cl, cr = FFV[(f.flav, vec.flav)]
         m, wd = FERMION_MASS[f.flav]
+        if cl == cr:
+            return (f"cx<T> {name}[4]; {{ const R K[4] = {K}; "
+                    f"ffv_cur_fin_v<T>({dn[0]}, {dn[1]}, c.{cl}, K, c.{m}, c.{wd}, {name}); }}",
+                    FLOPS['ffv_cur_fin_v'])
         return (f"cx<T> {name}[4]; {{ const R K[4] = {K}; "
                 f"ffv_cur_fin<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{m}, c.{wd}, {name}); }}",
                 FLOPS['ffv_cur_fin'])
@@ -424,6 +437,10 @@ def emit_body(pd, coefs, order, bils, need, budget, fence_every=4):
         if len(nd) == 2:   # shared bilinear . vector
             L.append(f"  {{ const cx<T> a = times_i(mdot({names[0]}, {names[1]}));")
             fl = FLOPS['amp_dot']
+        elif cl == cr:
+            L.append(f"  {{ const cx<T> a = ffv_amp_v<T>({names[0]}, {names[1]}, {names[2]}, "
+                     f"c.{cl});")
+            fl = FLOPS['ffv_amp_v']
         else:
             L.append(f"  {{ const cx<T> a = ffv_amp<T>({names[0]}, {names[1]}, {names[2]}, "
                      f"c.{cl}, c.{cr});")
@@ -689,12 +706,14 @@ def emit_adjoint_body(pd, coefs, order, bils, need, budget):
 # VGPRs, FP32 ones 8; the colour-flow amplitudes stay live besides them).
 # FP64 16, one helicity per lane: fewer recomputations outweigh a few
 # hundred bytes of spills (13: 19.1, 14: 19.4, 15 and 16: 19.5, 18: 19.3 M
-# MEs/s).  FP32 12, one helicity per lane, fits 256 registers: two waves
-# per SIMD (27.1 M MEs/s; 10: 22.6).  'f32m' is the FP32 body of the
-# event-per-lane kernel whose colour sum runs on the matrix cores (28: 23.8,
-# 36: 26.1).  The gradient kernel (gg -> t t~ g) takes the same time for
-# FP64 budgets 6 to 12.
-BUDGET = {'f64': 16, 'f32': 12, 'f32m': 36, 'a64': 8, 'a32': 12}
+# MEs/s; with the vector-like vertices 15 to 17 give 20.1-20.3).  FP32 13,
+# one helicity per lane, the largest budget that fits 256 registers (two
+# waves per SIMD): 11: 28.6, 12: 29.7, 13: 32.2 M MEs/s, 14 spills into
+# AGPRs (one wave per SIMD).  'f32m' is the FP32 body of the event-per-lane
+# kernel whose colour sum runs on the matrix cores (28: 23.8, 36: 26.1).
+# The gradient kernel (gg -> t t~ g) takes the same time for FP64 budgets
+# 6 to 12.
+BUDGET = {'f64': 16, 'f32': 13, 'f32m': 36, 'a64': 8, 'a32': 12}
 # processes with a generated reverse-mode (adjoint) body for the gradient kernel
 GRAD_PROCESSES = ('eemumu', 'ggtt', 'ggttg')
 # local-search moves over the diagram order (gg -> t t~ g g at FP64 budget 16:
