@@ -187,7 +187,7 @@ static int filter_helicities(mg_handle* h) {
   const int nhel = 1 << npar;
   const int64_t n = 64;
   double *mom = nullptr, *wgt = nullptr, *mehel = nullptr;
-  const size_t mom_bytes = sizeof(double) * (size_t)npar * 4 * NEPPM;
+  const size_t mom_bytes = sizeof(double) * (size_t)npar * 4 * ((n + NEPPM - 1) / NEPPM) * NEPPM;
   if (hipMalloc(&mom, mom_bytes) != hipSuccess || hipMalloc(&wgt, sizeof(double) * n) != hipSuccess ||
       hipMalloc(&mehel, sizeof(double) * n * nhel) != hipSuccess) {
     (void)hipFree(mom);

@@ -10,8 +10,12 @@ namespace mg {
 
 // AoSoA page sizes (Sec. IV.b "AOSOA"): 64 events per page, so one wave64
 // reads one (particle, component) row of a momentum page as 512 contiguous
-// bytes -- a fully coalesced load.
-constexpr int NEPPM = 64;
+// bytes -- a fully coalesced load.  -DMG_NEPPM=n builds another momentum
+// page size (1: plain AoS) for the paper's page-size comparison.
+#ifndef MG_NEPPM
+#define MG_NEPPM 64
+#endif
+constexpr int NEPPM = MG_NEPPM;
 constexpr int NEPPR = 64;
 
 // Couplings and masses handed to the kernels by value (Sec. IV.c keeps
