@@ -23,7 +23,7 @@ struct P_eemumu {
 
 int launch_sigmakin_eemumu_f64(const MeArgs& a, const double* mom, int64_t nevt, double* me,
                               const double* wgt, double* evtw, double* mehel, hipStream_t s) {
-  return sigmakin_launch<P_eemumu, double, 256>(a, a.c64, mom, nevt, me, wgt, evtw, mehel, s);
+  return sigmakin_launch<P_eemumu, double, MG_EPL_BLOCK>(a, a.c64, mom, nevt, me, wgt, evtw, mehel, s);
 }
 
 }  // namespace mg

@@ -23,7 +23,7 @@ struct P_ggttg {
 
 int launch_sigmakin_ggttg_f32(const MeArgs& a, const double* mom, int64_t nevt, double* me,
                               const double* wgt, double* evtw, double* mehel, hipStream_t s) {
-  return sigmakin_launch<P_ggttg, float, 256>(a, a.c32, mom, nevt, me, wgt, evtw, mehel, s);
+  return sigmakin_launch<P_ggttg, float, MG_EPL_BLOCK>(a, a.c32, mom, nevt, me, wgt, evtw, mehel, s);
 }
 
 }  // namespace mg

@@ -16,6 +16,12 @@
 #include "common.h"
 #include "internal.h"
 
+// Threads per block of the event-per-lane kernel (e+e- -> mu+mu-, g g -> t
+// t~, g g -> t t~ g); -DMG_EPL_BLOCK=n builds another block size.
+#ifndef MG_EPL_BLOCK
+#define MG_EPL_BLOCK 256
+#endif
+
 namespace mg {
 
 // Workgroups are handed to the 8 XCDs of the chip in turn (block b to XCD
