@@ -7,8 +7,9 @@
   the live set never exceeds the budget.
 * The order search returns a permutation of the diagrams whose cost does
   not exceed the starting order's.
-* The recorded schedules of the committed generated code respect the same
-  bounds, and its process constants match the diagram and colour counts.
+* The recorded schedules of the generated code (written by the build)
+  respect the same bounds, and its process constants match the diagram and
+  colour counts.
 * bench.py refuses more than one GPU with a message and exit status 2.
 """
 import json
@@ -50,10 +51,12 @@ def test_order_search_is_a_permutation_that_does_not_cost_more(ggttg):
     assert cost == emit.schedule_cost(best, need, 8) <= emit.schedule_cost(order, need, 8)
 
 
-def test_committed_generated_code_metadata():
+def test_generated_code_metadata():
     from paper_2106_12631_amd.gen import emit
-    meta = json.load(open(os.path.join(ROOT, 'paper_2106_12631_amd', 'csrc', 'generated',
-                                       'meta.json')))
+    path = os.path.join(ROOT, 'paper_2106_12631_amd', 'csrc', 'generated', 'meta.json')
+    if not os.path.exists(path):
+        pytest.skip("the generated code is written by the build (paper_2106_12631_amd.build)")
+    meta = json.load(open(path))
     want = {'eemumu': (4, 1, 2, 4), 'ggtt': (4, 2, 3, 256), 'ggttg': (5, 6, 16, 256),
             'ggttgg': (6, 24, 123, 512)}
     for proc, (npar, ncol, ndiag, iden) in want.items():
