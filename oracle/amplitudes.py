@@ -141,8 +141,9 @@ def amp_ggtt_explicit(p, hel, prm, colours):
     g = prm.gs
     gl, ubt, vtb, p3 = qcd_externals(p, hel, prm.mt)
     (_, e1, k1), (_, e2, k2) = gl
-    S13 = fermion_propagator(p3 - k1, prm.mt, prm.wt)
-    S23 = fermion_propagator(p3 - k2, prm.mt, prm.wt)
+    # both top propagators separate the two incoming gluons: t-channel
+    S13 = fermion_propagator(p3 - k1, prm.mt, prm.top_width(True))
+    S23 = fermion_propagator(p3 - k2, prm.mt, prm.top_width(True))
     # t-channel: gluon 0 next to the top
     L1 = torch.einsum('na,nab,nbc,ncd,nd->n', ubt, 1j * g * slash(e1), S13,
                       1j * g * slash(e2), vtb)
@@ -165,6 +166,11 @@ def amp_ggtt_explicit(p, hel, prm, colours):
 # --------------------------------------------------------------------------
 # recursion over gluon subsets, explicit adjoint colour indices
 # --------------------------------------------------------------------------
+
+def _n_in(S):
+    """Incoming gluons (legs 0 and 1) among the gluon legs S."""
+    return sum(1 for l in S if l < 2)
+
 
 def _subsets(items):
     items = tuple(items)
@@ -251,7 +257,8 @@ def amp_full_colour(p, hel, prm, gcol, tcol, tbcol, override=None):
         for S2 in _subsets(S):
             S1 = tuple(x for x in S if x not in S2)
             acc = acc + attach(U[S1], J[S2])
-        prop = fermion_propagator(p3 - KS, prm.mt, prm.wt)
+        # t-channel: exactly one incoming gluon (legs 0, 1) on the t side
+        prop = fermion_propagator(p3 - KS, prm.mt, prm.top_width(_n_in(S) == 1))
         U[S] = torch.einsum('...jy,...yz->...jz', acc, prop)
     amp = 0
     for S2 in _subsets(allS):
@@ -333,7 +340,7 @@ def dual_amplitudes(p, hel, prm, override=None):
                 for v, jv in J[S2].items():
                     _add(acc, u + v, torch.einsum('...a,...ab->...b', Uu,
                                                   1j * g * slash(jv)))
-        prop = fermion_propagator(p3 - K[S], prm.mt, prm.wt)
+        prop = fermion_propagator(p3 - K[S], prm.mt, prm.top_width(_n_in(S) == 1))
         U[S] = {w: torch.einsum('...a,...ab->...b', r, prop) for w, r in acc.items()}
     A = {}
     for S2 in _subsets(allS):

@@ -34,10 +34,12 @@ def stats(f):
             float(fin.size))
 
 
-def xsec(st, n, sqrts, nfinal):
-    """sigma and its Monte Carlo error [pb] from stats() of n events."""
+def xsec(st, n, sqrts, nfinal, weights_with_2pi=False):
+    """sigma and its Monte Carlo error [pb] from stats() of n events;
+    weights_with_2pi: the weights already carry (2 pi)^(4 - 3 nfinal)."""
     s = sqrts * sqrts
-    scale = HBARC2_PB * (2.0 * math.pi) ** (4 - 3 * nfinal) / (2.0 * s)
+    twopi = 1.0 if weights_with_2pi else (2.0 * math.pi) ** (4 - 3 * nfinal)
+    scale = HBARC2_PB * twopi / (2.0 * s)
     mean = st[0] / n
     var = max(st[1] / n - mean * mean, 0.0)
     err = math.sqrt(var / (n - 1)) if n > 1 else float('inf')

@@ -18,6 +18,7 @@ Two colour treatments are offered for g g -> t t~ + n g:
   basis assignments squared and summed (plain definition; small samples).
 """
 import itertools
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -25,7 +26,7 @@ import torch
 
 from . import amplitudes as amp
 from . import colour, philox, rambo
-from .params import DEFAULT, Params
+from .params import DEFAULT, WEIGHT_2PI, Params
 
 F64 = torch.float64
 C128 = torch.complex128
@@ -132,11 +133,21 @@ def matrix_element(proc, p, prm=DEFAULT, colour_mode='dual', chunk=256):
     return torch.cat(outs) if outs else torch.zeros(0, dtype=F64)
 
 
+def phase_space(proc, r, prm=DEFAULT):
+    """RAMBO momenta (nevt, npar, 4) and weights (nevt,) for uniforms r;
+    with the WEIGHT_2PI flag the weights carry (2 pi)^(4 - 3 nfinal)."""
+    proc = PROCESSES[proc] if isinstance(proc, str) else proc
+    p, w = rambo.event_momenta(r, prm.sqrts, proc.final_masses(prm))
+    if prm.flags & WEIGHT_2PI:
+        w = w * (2.0 * math.pi) ** (4 - 3 * proc.nfinal)
+    return p, w
+
+
 def sample(proc, seed, evt_offset, nevt, prm=DEFAULT):
     """Randoms (nevt, nrnd), momenta (nevt, npar, 4), weights (nevt,)."""
     proc = PROCESSES[proc] if isinstance(proc, str) else proc
     r = torch.from_numpy(philox.uniforms(seed, evt_offset, nevt, proc.nrnd))
-    p, w = rambo.event_momenta(r, prm.sqrts, proc.final_masses(prm))
+    p, w = phase_space(proc, r, prm)
     return r, p, w
 
 
@@ -151,7 +162,7 @@ def event_weight_and_grad(proc, r, prm=DEFAULT):
     """
     proc = PROCESSES[proc] if isinstance(proc, str) else proc
     r = r.detach().to(F64).clone().requires_grad_(True)
-    p, w = rambo.event_momenta(r, prm.sqrts, proc.final_masses(prm))
+    p, w = phase_space(proc, r, prm)
     me = matrix_element(proc, p, prm, chunk=max(1, r.shape[0]))
     f = me * w
     (gf,) = torch.autograd.grad(f.sum(), r, retain_graph=True)
