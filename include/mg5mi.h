@@ -72,6 +72,18 @@ typedef enum {
  *   MG_MIXED_F32MFMA  as MG_MIXED with FP32 MFMA operands for every process */
 typedef enum { MG_FP64 = 0, MG_FP32AMP = 1, MG_MIXED = 2, MG_MIXED_F32MFMA = 3 } mg_prec_t;
 
+/* bits of mg_params_t.flags (Sec. IV.c: physics parameters of the kernels;
+ * the paper leaves both points open):
+ *   MG_FLAG_TCHANNEL_ZERO_WIDTH  top propagators with exactly one incoming
+ *       particle on each side (t- and u-channel) get zero width; the others
+ *       keep wt.  A width in a spacelike propagator breaks gauge invariance
+ *       at O(wt); by default every top propagator carries wt.
+ *   MG_FLAG_WEIGHT_2PI  RAMBO weights carry (2 pi)^(4 - 3 nfinal), i.e. the
+ *       measure prod d^3p/((2 pi)^3 2E) (2 pi)^4 delta^4; mg_xsec then adds
+ *       no 2 pi factor of its own. */
+#define MG_FLAG_TCHANNEL_ZERO_WIDTH 1
+#define MG_FLAG_WEIGHT_2PI 2
+
 /* physics inputs; couplings are derived in mg_create (sin^2 theta_W in the
  * G_F scheme from alpha, G_F and mZ) */
 typedef struct {
@@ -79,8 +91,9 @@ typedef struct {
   double alpha_inv; /* 1/alpha */
   double gfermi;    /* G_F [GeV^-2] */
   double mZ, wZ;    /* Z mass and width [GeV] */
-  double mt, wt;    /* top mass and width [GeV]; wt may be 0 */
+  double mt, wt;    /* top mass and width [GeV]; mt and wt may be 0 */
   double alphas;    /* strong coupling (fixed) */
+  int flags;        /* MG_FLAG_* bits; unknown bits give MG_EINVAL */
 } mg_params_t;
 
 typedef struct {
@@ -102,7 +115,8 @@ typedef struct mg_handle mg_handle_t;
  * Derives couplings, uploads small tables and determines the nonzero
  * helicities on 64 internally sampled events (synchronises the device).
  * prm == NULL selects the defaults (sqrt(s)=1500, 1/alpha=132.5,
- * G_F=1.16639e-5, mZ=91.188, wZ=2.441, mt=173, wt=1.49, alpha_s=0.118).
+ * G_F=1.16639e-5, mZ=91.188, wZ=2.441, mt=173, wt=1.49, alpha_s=0.118,
+ * flags=0).  The parameters are copied: prm may be freed afterwards.
  * Errors: MG_EINVAL, MG_ENOTSUP, MG_ENOPHASE, MG_ENOMEM, MG_EHIP. */
 int mg_create(int proc, int prec, const mg_params_t* prm, mg_handle_t** out);
 int mg_destroy(mg_handle_t* h);
@@ -118,7 +132,8 @@ int mg_rng(const mg_handle_t* h, uint64_t seed, int64_t evt_offset, int64_t nevt
 /* RAMBO phase space (Sec. IV.a/IV.b phase-space sampler; Kleiss, Stirling,
  * Ellis 1986): rnd (AoSoA) -> mom (AoSoA, all npar particles, initial
  * momenta along +-z) and weights wgt[nevt] (phase-space volume measure
- * prod d^3p/(2E) delta^4, no 2pi factors, no flux).  Massive final states
+ * prod d^3p/(2E) delta^4, no 2pi factors unless MG_FLAG_WEIGHT_2PI, no
+ * flux).  Massive final states
  * by Newton rescaling in FP64; a non-converged event gets a NaN weight. */
 int mg_rambo(const mg_handle_t* h, const double* rnd, int64_t nevt, double* mom, double* wgt,
              void* stream);
@@ -170,7 +185,9 @@ int mg_xsec_stats(const double* f, int64_t n, double* stats, void* stream);
 /* Host: cross section and Monte Carlo error in pb from stats copied to the
  * host, for n events of h's process:
  *   sigma = (hbar c)^2 (2 pi)^(4 - 3 nfinal) / (2 s) * stats[0] / n
- * (massless partons at fixed sqrt(s); RAMBO weights without 2 pi factors),
+ * (massless partons at fixed sqrt(s); RAMBO weights without 2 pi factors;
+ * with MG_FLAG_WEIGHT_2PI the weights already carry them and the factor
+ * (2 pi)^(4 - 3 nfinal) is left out),
  *   error = same factor * sqrt((stats[1]/n - (stats[0]/n)^2) / (n - 1)).
  * Non-finite events count as zero.  MG_EINVAL for n < 2 or null pointers. */
 int mg_xsec(const mg_handle_t* h, const double* stats_host, int64_t n, double* sigma_pb,

@@ -22,11 +22,16 @@ PRECISIONS = {'fp64': 0, 'fp32amp': 1, 'mixed': 2, 'mixed_f32mfma': 3}
 class Params(ctypes.Structure):
     _fields_ = [('sqrts', ctypes.c_double), ('alpha_inv', ctypes.c_double),
                 ('gfermi', ctypes.c_double), ('mZ', ctypes.c_double), ('wZ', ctypes.c_double),
-                ('mt', ctypes.c_double), ('wt', ctypes.c_double), ('alphas', ctypes.c_double)]
+                ('mt', ctypes.c_double), ('wt', ctypes.c_double), ('alphas', ctypes.c_double),
+                ('flags', ctypes.c_int)]
 
+
+# bits of Params.flags (include/mg5mi.h)
+FLAG_TCHANNEL_ZERO_WIDTH = 1
+FLAG_WEIGHT_2PI = 2
 
 DEFAULT_PARAMS = dict(sqrts=1500.0, alpha_inv=132.5, gfermi=1.16639e-5, mZ=91.188, wZ=2.441,
-                      mt=173.0, wt=1.49, alphas=0.118)
+                      mt=173.0, wt=1.49, alphas=0.118, flags=0)
 
 
 class Layout(ctypes.Structure):

@@ -145,6 +145,7 @@ static void derive(mg_handle* h) {
   c.czr = -(e / swcw) * (-Q * sw2);
   c.mt = p.mt;
   c.wt = p.wt;
+  c.wtt = (p.flags & MG_FLAG_TCHANNEL_ZERO_WIDTH) ? 0.0 : p.wt;
   c.mz = p.mZ;
   c.wz = p.wZ;
   h->me.c64 = c;
@@ -156,6 +157,7 @@ static void derive(mg_handle* h) {
   f.czr = (float)c.czr;
   f.mt = c.mt;
   f.wt = c.wt;
+  f.wtt = c.wtt;
   f.mz = c.mz;
   f.wz = c.wz;
   h->me.c32 = f;
@@ -169,6 +171,7 @@ static void derive(mg_handle* h) {
   for (int k = 2; k <= nf - 1; ++k) fact1 *= k;
   for (int k = 2; k <= nf - 2; ++k) fact2 *= k;
   r.w0 = pow(pi / 2.0, nf - 1) * pow(s, nf - 2) / (fact1 * fact2);
+  if (p.flags & MG_FLAG_WEIGHT_2PI) r.w0 *= pow(2.0 * pi, 4 - 3 * nf);
   double msum = 0.0;
   for (int i = 0; i < 4; ++i) r.m2[i] = 0.0;
   if (h->proc != MG_EEMUMU) {
@@ -226,10 +229,11 @@ extern "C" {
 int mg_create(int proc, int prec, const mg_params_t* prm, mg_handle_t** out) {
   if (!out || proc < 0 || proc > 3 || prec < 0 || prec > 3) return MG_EINVAL;
   *out = nullptr;
-  mg_params_t p = {1500.0, 132.5, 1.16639e-5, 91.188, 2.441, 173.0, 1.49, 0.118};
+  mg_params_t p = {1500.0, 132.5, 1.16639e-5, 91.188, 2.441, 173.0, 1.49, 0.118, 0};
   if (prm) p = *prm;
   if (!(p.sqrts > 0) || !(p.alpha_inv > 0) || !(p.gfermi > 0) || !(p.mZ > 0) || p.wZ < 0 ||
-      p.mt < 0 || p.wt < 0 || !(p.alphas > 0))
+      p.mt < 0 || p.wt < 0 || !(p.alphas > 0) ||
+      (p.flags & ~(MG_FLAG_TCHANNEL_ZERO_WIDTH | MG_FLAG_WEIGHT_2PI)) != 0)
     return MG_EINVAL;
   if (proc != MG_EEMUMU && 2.0 * p.mt >= p.sqrts) return MG_ENOPHASE;
   mg_handle* h = new (std::nothrow) mg_handle();
@@ -373,7 +377,8 @@ int mg_xsec(const mg_handle_t* h, const double* st, int64_t n, double* sigma_pb,
   const int nfinal = PROC_INFO[h->proc].npar - 2;
   const double s = h->prm.sqrts * h->prm.sqrts;
   const double hbarc2_pb = 0.3893793721e9;
-  const double scale = hbarc2_pb * pow(2.0 * M_PI, 4 - 3 * nfinal) / (2.0 * s);
+  const double twopi = (h->prm.flags & MG_FLAG_WEIGHT_2PI) ? 1.0 : pow(2.0 * M_PI, 4 - 3 * nfinal);
+  const double scale = hbarc2_pb * twopi / (2.0 * s);
   const double mean = st[0] / (double)n;
   double var = st[1] / (double)n - mean * mean;
   if (var < 0.0) var = 0.0;

@@ -27,6 +27,7 @@ struct Couplings {
   T cqed;           // photon-lepton coupling -e Q
   T czl, czr;       // Z-lepton chiral couplings
   double mt, wt;    // top mass and width
+  double wtt;       // width of t- and u-channel top propagators (wt, or 0)
   double mz, wz;    // Z mass and width
 };
 

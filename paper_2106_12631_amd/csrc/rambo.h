@@ -4,7 +4,10 @@
 // Four uniforms per final-state particle give an isotropic massless q_i
 // with energy -ln(r2 r3); the q_i are boosted to the rest frame of their sum
 // and scaled to sqrt(s); masses are introduced by a Newton solve for the
-// common scale xi of the three-momenta, in FP64.  Templated on the real
+// common scale xi of the three-momenta, in FP64.  The boost is written with
+// the pairwise Minkowski products of the q_i (identical to the published
+// boost in exact arithmetic; its direct form loses ~gamma^2 of the digits,
+// gamma = Q^0/M, when the q_i are nearly collinear).  Templated on the real
 // type R: double, or dual<double> to carry the derivative with respect to
 // one uniform (forward mode).  For duals the Newton solve runs on the values
 // and xi's derivative follows from the implicit-function theorem applied to
@@ -40,7 +43,7 @@ template <int NF, typename R>
 __device__ __forceinline__ bool rambo(const R (&r)[4 * NF], const RamboArgs& a,
                                       R (&p)[NF + 2][4], R& w) {
   const double twopi = 6.283185307179586476925286766559;
-  R q[NF][4];
+  R q0[NF], n[NF][3];
   R Q[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int i = 0; i < NF; ++i) {
@@ -48,29 +51,46 @@ __device__ __forceinline__ bool rambo(const R (&r)[4 * NF], const RamboArgs& a,
     const R st = sqrt(1.0 - c * c);
     R sph, cph;
     sincos(twopi * r[4 * i + 1], &sph, &cph);
-    const R q0 = -log(r[4 * i + 2] * r[4 * i + 3]);
-    q[i][0] = q0;
-    q[i][1] = q0 * st * cph;
-    q[i][2] = q0 * st * sph;
-    q[i][3] = q0 * c;
+    q0[i] = -log(r[4 * i + 2] * r[4 * i + 3]);
+    n[i][0] = st * cph;
+    n[i][1] = st * sph;
+    n[i][2] = c;
+    Q[0] += q0[i];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) Q[m] += q[i][m];
+    for (int m = 0; m < 3; ++m) Q[m + 1] += q0[i] * n[i][m];
   }
-  const R M = sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
-  const R b1 = -Q[1] / M, b2 = -Q[2] / M, b3 = -Q[3] / M;
-  const R gam = Q[0] / M;
-  const R aa = 1.0 / (1.0 + gam);
+  // Boost to the rest frame of Q from the Minkowski products of the massless
+  // q_i, q_i.q_j = q_i^0 q_j^0 |n_i - n_j|^2 / 2 (exact for nearly collinear
+  // q_i, where Q^0^2 - |Q|^2 cancels): M^2 = sum_{i != j} q_i.q_j, rest-frame
+  // energies E_i = q_i.Q / M, three-momenta q_i - Q (q_i^0 + E_i)/(Q^0 + M).
+  R EM[NF];
+#pragma unroll
+  for (int i = 0; i < NF; ++i) EM[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < NF; ++i)
+#pragma unroll
+    for (int j = i + 1; j < NF; ++j) {
+      const R d0 = n[i][0] - n[j][0], d1 = n[i][1] - n[j][1], d2 = n[i][2] - n[j][2];
+      const R dij = 0.5 * q0[i] * q0[j] * (d0 * d0 + d1 * d1 + d2 * d2);
+      EM[i] += dij;
+      EM[j] += dij;
+    }
+  R M2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NF; ++i) M2 += EM[i];
+  const R M = sqrt(M2);
   const R x = a.sqrts / M;
+  const R Q0M = Q[0] + M;
   const double h = 0.5 * a.sqrts;
   p[0][0] = h; p[0][1] = 0.0; p[0][2] = 0.0; p[0][3] = h;
   p[1][0] = h; p[1][1] = 0.0; p[1][2] = 0.0; p[1][3] = -h;
 #pragma unroll
   for (int i = 0; i < NF; ++i) {
-    const R bq = b1 * q[i][1] + b2 * q[i][2] + b3 * q[i][3];
-    p[i + 2][0] = x * (gam * q[i][0] + bq);
-    p[i + 2][1] = x * (q[i][1] + b1 * q[i][0] + aa * bq * b1);
-    p[i + 2][2] = x * (q[i][2] + b2 * q[i][0] + aa * bq * b2);
-    p[i + 2][3] = x * (q[i][3] + b3 * q[i][0] + aa * bq * b3);
+    const R E = EM[i] / M;
+    const R t = (q0[i] + E) / Q0M;
+    p[i + 2][0] = x * E;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) p[i + 2][m + 1] = x * (q0[i] * n[i][m] - Q[m + 1] * t);
   }
   w = a.w0;
   if (!a.massive) return true;

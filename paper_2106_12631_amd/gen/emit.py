@@ -278,6 +278,16 @@ def _coef_expr(coef, amp):
     return f"+ cx<T>{{(T){c.real!r}, (T){c.imag!r}}} * {amp}"
 
 
+def _fermion_width(f, n, parts):
+    """(mass, width) coupling names of the propagator of fermion current n:
+    a top propagator with exactly one incoming particle on each side (t- or
+    u-channel) takes the width 'wtt', which the zero-width flag sets to 0."""
+    m, wd = FERMION_MASS[f.flav]
+    if wd == 'wt' and sum(1 for l in n.legs if parts[l][1] == IN) == 1:
+        wd = 'wtt'
+    return m, wd
+
+
 def _node_code(n, name, dn, parts):
     """C++ statement computing wavefunction n into `name`; dn = names of its
     inputs in op order.  Returns (code, flops)."""
@@ -300,7 +310,7 @@ def _node_code(n, name, dn, parts):
     if op[0] == 'ffv_fout':
         f, vec = op[1], op[2]
         cl, cr = FFV[(f.flav, vec.flav)]
-        m, wd = FERMION_MASS[f.flav]
+        m, wd = _fermion_width(f, n, parts)
         if cl == cr:
             return (f"cx<T> {name}[4]; {{ const R K[4] = {K}; "
                     f"ffv_cur_fout_v<T>({dn[0]}, {dn[1]}, c.{cl}, K, c.{m}, c.{wd}, {name}); }}",
@@ -311,7 +321,7 @@ def _node_code(n, name, dn, parts):
     if op[0] == 'ffv_fin':
         vec, f = op[1], op[2]
         cl, cr = FFV[(f.flav, vec.flav)]
-        m, wd = FERMION_MASS[f.flav]
+        m, wd = _fermion_width(f, n, parts)
         if cl == cr:
             return (f"cx<T> {name}[4]; {{ const R K[4] = {K}; "
                     f"ffv_cur_fin_v<T>({dn[0]}, {dn[1]}, c.{cl}, K, c.{m}, c.{wd}, {name}); }}",
@@ -669,14 +679,14 @@ def emit_adjoint_body(pd, coefs, order, bils, need, budget):
                 elif op[0] == 'ffv_fout':
                     f, vec = op[1], op[2]
                     cl, cr = FFV[(f.flav, vec.flav)]
-                    m, wd = FERMION_MASS[f.flav]
+                    m, wd = _fermion_width(f, n, parts)
                     L.append(f"    adj_ffv_cur_fout<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{m}, c.{wd}, "
                              f"{wb}, {accs[f.idx]}, {accs[vec.idx]}, Kb);")
                     execd += ADJ_FLOPS['ffv_cur_fout']
                 elif op[0] == 'ffv_fin':
                     vec, f = op[1], op[2]
                     cl, cr = FFV[(f.flav, vec.flav)]
-                    m, wd = FERMION_MASS[f.flav]
+                    m, wd = _fermion_width(f, n, parts)
                     L.append(f"    adj_ffv_cur_fin<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, K, c.{m}, c.{wd}, "
                              f"{wb}, {accs[vec.idx]}, {accs[f.idx]}, Kb);")
                     execd += ADJ_FLOPS['ffv_cur_fin']
