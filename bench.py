@@ -3,14 +3,27 @@
 
 One step = one pass of the whole path over one batch of synthetic events:
 random numbers + RAMBO (fused sampler kernel) and SIGMAKIN (helicity
-amplitudes, colour-flow amplitudes, colour sum, helicity sum), for the
-gg -> t t~ g g workload (2^19 events, seed 3, sqrt(s) = 1500 GeV).
-The headline value is the FP64 path; the FP32-amplitude path is measured
-beside it.  Prints one JSON line.
+amplitudes, colour-flow amplitudes, colour sum, helicity sum).  The headline
+is the gg -> t t~ g g workload (2^19 events, seed 3, sqrt(s) = 1500 GeV) in
+FP64; every benchmark workload is measured beside it (`variants`):
+
+  e+e- -> mu+mu-  16384 events, seed 0     FP64
+  g g -> t t~     2^20 events, seed 1      FP64, FP32 amplitudes
+  g g -> t t~ g   2^20 events, seed 2      mixed (FP32 MFMA colour sum), FP64
+  g g -> t t~ g g 2^19 events, seed 3      FP64, mixed (BF16-split MFMA), FP32 amplitudes
+  gradient        g g -> t t~ g, 2^18 events, seed 4: d(w |M|^2)/dr, FP64 and FP32 amplitudes
+  plateau         e+e- -> mu+mu-, 2^24 events, seed 0, FP64 (throughput plateau)
+
+Three timing scopes per variant (medians over the timed steps, as the
+paper's 12 iterations): SIGMAKIN only, sampler + SIGMAKIN, and + the copy of
+the matrix elements to pinned host memory.  The oracle is timed per
+workload on the host's cores (1 core and P cores, each for a bounded time,
+worker start-up and imports excluded), and the GPU results of the same
+events are compared with the oracle's (end to end from the uniforms, and on
+the oracle's momenta).  Prints one JSON line.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -26,6 +39,19 @@ PEAK_FP64_VALU = 78.6e12       # FLOP/s, MI355X vector FP64 (256 CU x 4 SIMD x 1
 # wave instruction per 4 cycles per SIMD, so the FP32 forms are priced
 # against the published figure rather than the FP64 rate.
 PEAK_FP32_VALU = 157.3e12
+PEAK_MFMA = {'bf16': 2.5e15, 'f32': 157.3e12}  # dense FLOP/s, MI355X
+
+# (name, process, events, seed, precisions); the first precision of the
+# headline workload is the headline value
+WORKLOADS = [
+    ('eemumu', 'eemumu', 16384, 0, ('fp64',)),
+    ('ggtt', 'ggtt', 1 << 20, 1, ('fp64', 'fp32amp')),
+    ('ggttg', 'ggttg', 1 << 20, 2, ('mixed', 'fp64')),
+    ('ggttgg', 'ggttgg', 1 << 19, 3, ('fp64', 'mixed', 'fp32amp')),
+]
+HEADLINE = 'ggttgg'
+GRADIENT = ('ggttg', 1 << 18, 4, ('fp64', 'fp32amp'))
+PLATEAU = ('eemumu', 1 << 24, 0, 'fp64')
 
 
 # ----------------------------------------------------------------------------- HBM traffic
@@ -35,7 +61,6 @@ def kernel_source_hash(proc):
     the compiler flags.  HBM counters recorded under profiles/ are reported only
     while this hash matches the one they were taken with."""
     import hashlib
-    sys.path.insert(0, os.path.join(ROOT, 'paper_2106_12631_amd'))
     from paper_2106_12631_amd import build as _build
     csrc = os.path.join(ROOT, 'paper_2106_12631_amd', 'csrc')
     shared = ['colour_mfma.h', 'common.h', 'helas.h', 'internal.h', 'sigmakin_impl.h']
@@ -68,40 +93,100 @@ def recorded_traffic(proc, nevt):
 
 
 # ----------------------------------------------------------------------------- CPU baseline
-def _oracle_chunk(task):
-    proc, seed, start, count = task
+def _oracle_eval(kind, proc, seed, start, count):
+    """The oracle on events [start, start + count): RNG + RAMBO + |M|^2
+    (kind 'me'), or f = w |M|^2 and its gradient by autograd (kind 'grad').
+    Returns arrays to compare the GPU with."""
+    from oracle import me as orc
+    if kind == 'me':
+        _, p, _ = orc.sample(proc, seed, start, count)
+        me = orc.matrix_element(proc, p, chunk=64)
+        return {'me': me.numpy(), 'p': p.numpy()}
+    r, _, _ = orc.sample(proc, seed, start, count)
+    f, g, _ = orc.event_weight_and_grad(proc, r)
+    return {'f': f.numpy(), 'grad': g.numpy()}
+
+
+def _oracle_worker(kind, proc, seed, start, tmin, barrier, queue):
+    import numpy as np
     import torch
     torch.set_num_threads(1)
-    from oracle import me as orc
+    _oracle_eval(kind, proc, seed, start, 1)  # imports and first-call set-up, not timed
+    barrier.wait()
     t0 = time.perf_counter()
-    _, p, _ = orc.sample(proc, seed, start, count)
-    orc.matrix_element(proc, p, chunk=64)
-    return count, time.perf_counter() - t0
+    n, chunk, parts = 0, 1, []
+    while True:
+        parts.append(_oracle_eval(kind, proc, seed, start + n, chunk))
+        n += chunk
+        el = time.perf_counter() - t0
+        if el >= tmin:
+            break
+        # aim the remaining chunks at the time limit
+        chunk = max(1, min(4 * chunk, int(n / el * (tmin - el)) + 1, 4096))
+    t1 = time.perf_counter()
+    out = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+    queue.put((start, n, t0, t1, out))
 
 
-def cpu_baseline(proc, seed, per_worker, workers):
-    """Oracle (as it stands) on a bounded sample, one process per core."""
+def oracle_timing(kind, proc, seed, workers, tmin, stride):
+    """The oracle on `workers` host cores, one process and one thread each,
+    every worker for at least tmin seconds on its own event range (worker w
+    from event w * stride).  Start-up and imports happen before a barrier;
+    the wall time runs from the first worker's start to the last one's
+    end.  Returns (events per second, events, wall, per-worker results)."""
     import multiprocessing as mp
-    tasks = [(proc, seed, w * per_worker, per_worker) for w in range(workers)]
     ctx = mp.get_context('fork')
-    t0 = time.perf_counter()
-    with ctx.Pool(workers) as pool:
-        res = pool.map(_oracle_chunk, tasks)
-    wall = time.perf_counter() - t0
-    n = sum(c for c, _ in res)
-    per_core = sum(c / t for c, t in res) / len(res)
-    cpu_model = ''
+    barrier = ctx.Barrier(workers)
+    queue = ctx.Queue()
+    procs = [ctx.Process(target=_oracle_worker,
+                         args=(kind, proc, seed, w * stride, tmin, barrier, queue))
+             for w in range(workers)]
+    for p in procs:
+        p.start()
+    res = [queue.get() for _ in procs]
+    for p in procs:
+        p.join()
+    n = sum(r[1] for r in res)
+    wall = max(r[3] for r in res) - min(r[2] for r in res)
+    return n / wall, n, wall, res
+
+
+def host_cores():
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
+
+
+def cpu_model():
     try:
         for line in open('/proc/cpuinfo'):
             if line.startswith('model name'):
-                cpu_model = line.split(':', 1)[1].strip()
-                break
+                return line.split(':', 1)[1].strip()
     except OSError:
         pass
-    return {"value": n / wall, "unit": "MEs/s", "cores": workers, "kind": "oracle",
-            "single_core_value": per_core, "cpu": cpu_model,
-            "sample": f"events 0..{n - 1} of the workload (seed {seed}): RNG + RAMBO + |M|^2, "
-                      f"{workers} processes x 1 thread, {wall:.1f} s wall"}
+    return ''
+
+
+def cpu_baselines(tmin, workers):
+    """Oracle rates per workload on 1 core and on `workers` cores, and the
+    oracle's results on the events it timed (for the GPU comparison)."""
+    out = {}
+    jobs = [(name, 'me', proc, nevt, seed) for name, proc, nevt, seed, _ in WORKLOADS]
+    jobs.append(('gradient', 'grad', GRADIENT[0], GRADIENT[1], GRADIENT[2]))
+    for name, kind, proc, nevt, seed in jobs:
+        r1, n1, w1, res1 = oracle_timing(kind, proc, seed, 1, tmin, 0)
+        stride = max(1, nevt // workers)
+        rp, npar, wp, resp = oracle_timing(kind, proc, seed, workers, tmin, stride)
+        out[name] = {
+            "single_core": {"value": r1, "events": n1, "seconds": w1},
+            "all_cores": {"value": rp, "events": npar, "seconds": wp, "cores": workers},
+            "results": [(s, n, o) for s, n, _, _, o in res1 + resp],
+        }
+        print(f"[bench] oracle {name}: {r1:.4g} /s on 1 core, {rp:.4g} /s on {workers} cores",
+              file=sys.stderr, flush=True)
+    return out
 
 
 # ----------------------------------------------------------------------------- GPU
@@ -113,7 +198,8 @@ def _median(x):
 
 def run_gpu(mg, torch, proc, prec, seed, nevt, steps, warmup):
     """Warm-up, then `steps` timed steps (sampler + SIGMAKIN) between two
-    device synchronisations; HIP events on the launching stream split each
+    device synchronisations; HIP events on the launching stream (torch's
+    current stream, on which the binding enqueues every call) split each
     step into its kernels.  Afterwards the same number of steps with the
     matrix elements copied to pinned host memory gives the paper's third
     timing scope (compute + device-to-host)."""
@@ -160,10 +246,7 @@ def run_gpu(mg, torch, proc, prec, seed, nevt, steps, warmup):
         "sample_sigmakin_dtoh": nevt / (_median(d2h_ms) / 1e3),
         "unit": "MEs/s (median over the timed steps)",
     }
-    return eng, wall, k_ms, nonfinite, scopes
-
-
-PEAK_MFMA = {'bf16': 2.5e15, 'f32': 157.3e12}  # dense FLOP/s, MI355X
+    return eng, wall, k_ms, nonfinite, scopes, me
 
 
 def mfma_work(ncol, nhel, prec, proc, seconds, nevt):
@@ -183,24 +266,61 @@ def mfma_work(ncol, nhel, prec, proc, seconds, nevt):
             "frac": achieved / peak}
 
 
-def run_gradient(mg, torch, prec, nevt, steps, warmup, seed=4):
+def _errors(err, n_above=1e-12):
+    import numpy as np
+    err = np.asarray(err)
+    if err.size == 0:
+        return None
+    return {"max": float(err.max()), "median": float(np.median(err)),
+            "above_1e-12": int((err > n_above).sum()), "events": int(err.size)}
+
+
+def parity_vs_oracle(eng, torch, me_gpu, nevt, orc_res):
+    """GPU against the oracle on the events the oracle timed (indices below
+    nevt): end to end (the GPU's own sampled events, same seed and index)
+    and on the oracle's momenta."""
+    import numpy as np
+    idx, me_o, p_o = [], [], []
+    for start, n, o in orc_res:
+        k = max(0, min(n, nevt - start))
+        idx.extend(range(start, start + k))
+        me_o.append(o['me'][:k])
+        p_o.append(o['p'][:k])
+    if not idx:
+        return None
+    me_o = np.concatenate(me_o)
+    p_o = torch.from_numpy(np.concatenate(p_o))
+    got = me_gpu[torch.tensor(idx, device=me_gpu.device)].cpu().numpy()
+    e2e = np.abs(got - me_o) / np.abs(me_o)
+    same = eng.sigmakin(eng.events_mom(p_o), len(idx)).cpu().numpy()
+    err_same = np.abs(same - me_o) / np.abs(me_o)
+    return {"end_to_end": _errors(e2e), "same_momenta": _errors(err_same)}
+
+
+def run_gradient(mg, torch, prec, nevt, seed, steps, warmup, orc_res):
     """Gradient workload: d(w |M|^2)/dr and d log w/dr for g g -> t t~ g,
-    timed beside the forward pass (RAMBO + SIGMAKIN) on the same uniforms."""
-    eng = mg.MEEngine('ggttg', prec)
+    timed beside the forward pass (RAMBO + SIGMAKIN) on the same uniforms;
+    the gradients of the oracle's events compared normwise."""
+    import numpy as np
+    eng = mg.MEEngine(GRADIENT[0], prec)
     rnd = eng.rng(seed, nevt)
     mom = eng.empty_mom(nevt)
     wgt = torch.empty(nevt, dtype=torch.float64, device=eng.device)
     me = torch.empty(nevt, dtype=torch.float64, device=eng.device)
+    stream = torch.cuda.current_stream()
 
     def timed(fn):
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        for a, b in evs:
+            a.record(stream)
             fn()
+            b.record(stream)
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / steps
+        return _median([a.elapsed_time(b) for a, b in evs]) / 1e3
 
     out = {}
 
@@ -213,9 +333,21 @@ def run_gradient(mg, torch, prec, nevt, steps, warmup, seed=4):
 
     t_grad = timed(grad)
     t_fwd = timed(fwd)
-    return {"events_per_s": nevt / t_grad, "ms_per_launch": t_grad * 1e3,
-            "forward_ms": t_fwd * 1e3, "gradient_over_forward": t_grad / t_fwd,
-            "nonfinite": eng.count_nonfinite(out['g'][0])}
+    res = {"events_per_s": nevt / t_grad, "ms_per_launch": t_grad * 1e3,
+           "forward_ms": t_fwd * 1e3, "gradient_over_forward": t_grad / t_fwd,
+           "nonfinite": eng.count_nonfinite(out['g'][0])}
+    if orc_res:
+        g_all = eng.rnd_events(out['g'][0], nevt)
+        errs = []
+        for start, n, o in orc_res:
+            k = max(0, min(n, nevt - start))
+            if k:
+                g = g_all[start:start + k].cpu().numpy()
+                ref = o['grad'][:k]
+                errs.append(np.linalg.norm(g - ref, axis=1) / np.linalg.norm(ref, axis=1))
+        if errs:
+            res["vs_oracle_normwise"] = _errors(np.concatenate(errs))
+    return res
 
 
 def main():
@@ -223,14 +355,13 @@ def main():
     ap.add_argument('--gpus', type=int, default=1)
     ap.add_argument('--steps', type=int, default=12)
     ap.add_argument('--warmup', type=int, default=2)
-    ap.add_argument('--process', default='ggttgg')
-    ap.add_argument('--nevt', type=int, default=1 << 19)
-    ap.add_argument('--seed', type=int, default=3)
-    ap.add_argument('--precisions', default='fp64,mixed,fp32amp')
+    ap.add_argument('--only', default='',
+                    help='comma-separated workload names to run (default: all)')
     ap.add_argument('--no-cpu-baseline', action='store_true')
-    ap.add_argument('--cpu-events-per-worker', type=int, default=96)
-    ap.add_argument('--no-gradient', action='store_true',
-                    help='skip the gradient workload (g g -> t t~ g, 2^18 events)')
+    ap.add_argument('--cpu-seconds', type=float, default=5.0,
+                    help='minimum oracle time per workload, on 1 core and on all cores')
+    ap.add_argument('--no-gradient', action='store_true')
+    ap.add_argument('--no-plateau', action='store_true')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a plain 1 GiB device-to-device copy (HBM counter calibration)')
     args = ap.parse_args()
@@ -249,69 +380,113 @@ def main():
               f"(events are independent: they would shard as one contiguous event range "
               f"per GPU)", file=sys.stderr)
         sys.exit(2)
+    only = set(filter(None, args.only.split(',')))
+    workloads = [w for w in WORKLOADS if not only or w[0] in only]
+    do_grad = not args.no_gradient and (not only or 'gradient' in only)
+    do_plateau = not args.no_plateau and (not only or 'plateau' in only)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        workers = max(1, min(16, os.cpu_count() or 1))
-        cpu = cpu_baseline(args.process, args.seed, args.cpu_events_per_worker, workers)
+    # the oracle runs first, in forked worker processes, before this process
+    # touches the GPU
+    cores = host_cores()
+    cpu = cpu_baselines(args.cpu_seconds, cores) if not args.no_cpu_baseline else {}
 
     import torch
     import paper_2106_12631_amd as mg
-    meta = json.load(open(os.path.join(ROOT, 'paper_2106_12631_amd', 'csrc', 'generated',
-                                       'meta.json')))[args.process]
-    traffic = recorded_traffic(args.process, args.nevt)
-    results = {}
-    for prec in args.precisions.split(','):
-        eng, wall, k_ms, nonfinite, scopes = run_gpu(mg, torch, args.process, prec, args.seed,
-                                                     args.nevt, args.steps, args.warmup)
-        nhel = eng.layout.nhel_good
-        flops_evt = (meta['flops_amp_per_hel'] + meta['flops_colour_per_hel']) * nhel
-        k_avg = sum(k_ms) / len(k_ms) / 1e3
-        achieved = flops_evt * args.nevt / k_avg
-        peak = PEAK_FP64_VALU if prec == 'fp64' else PEAK_FP32_VALU
-        results[prec] = {
-            "value": args.nevt * args.steps / wall,
-            "ms_per_step": wall / args.steps * 1e3,
-            "sigmakin_ms": k_avg * 1e3,
-            "sigmakin_MEs_per_s": args.nevt / k_avg,
-            "nonfinite": nonfinite,
-            "scopes": scopes,
-            "roofline": {"bound": "alu", "achieved": achieved / 1e12,
-                         "peak": peak / 1e12, "unit": "TFLOP/s",
-                         "frac": achieved / peak, "traffic": traffic.get(prec),
-                         "flops_per_event": flops_evt},
-        }
-        if prec.startswith('mixed'):
-            results[prec]["mfma"] = mfma_work(meta['ncol'], nhel, prec, args.process, k_avg,
-                                              args.nevt)
+    metas = json.load(open(os.path.join(ROOT, 'paper_2106_12631_amd', 'csrc', 'generated',
+                                        'meta.json')))
+    variants = {}
+    for name, proc, nevt, seed, precs in workloads:
+        meta = metas[proc]
+        traffic = recorded_traffic(proc, nevt)
+        for prec in precs:
+            print(f"[bench] {name} {prec} {nevt} events", file=sys.stderr, flush=True)
+            eng, wall, k_ms, nonfinite, scopes, me = run_gpu(mg, torch, proc, prec, seed, nevt,
+                                                             args.steps, args.warmup)
+            nhel = eng.layout.nhel_good
+            flops_evt = (meta['flops_amp_per_hel'] + meta['flops_colour_per_hel']) * nhel
+            k_avg = sum(k_ms) / len(k_ms) / 1e3
+            achieved = flops_evt * nevt / k_avg
+            peak = PEAK_FP64_VALU if prec == 'fp64' else PEAK_FP32_VALU
+            v = {
+                "workload": f"{proc} {nevt} events seed {seed}",
+                "precision": prec,
+                "value": nevt * args.steps / wall,
+                "unit": "MEs/s (sampler + SIGMAKIN, wall clock over the timed steps)",
+                "ms_per_step": wall / args.steps * 1e3,
+                "sigmakin_ms": k_avg * 1e3,
+                "nonfinite": nonfinite,
+                "scopes": scopes,
+                "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                             "peak": peak / 1e12, "unit": "TFLOP/s",
+                             "frac": achieved / peak, "traffic": traffic.get(prec),
+                             "flops_per_event": flops_evt},
+            }
+            if prec.startswith('mixed'):
+                v["mfma"] = mfma_work(meta['ncol'], nhel, prec, proc, k_avg, nevt)
+            if name in cpu:
+                v["vs_oracle"] = parity_vs_oracle(eng, torch, me, nevt, cpu[name]["results"])
+            variants[f"{name}_{prec}"] = v
+            del eng, me
+            torch.cuda.empty_cache()
     gradient = None
-    if not args.no_gradient:
-        gradient = {"workload": "ggttg 262144 events seed 4: d(w |M|^2)/dr, d log w/dr "
-                                "(12 uniforms per event)"}
-        for prec in ('fp64', 'fp32amp'):
-            gradient[prec] = run_gradient(mg, torch, prec, 1 << 18, max(1, args.steps // 2), 1)
-    head = results.get('fp64') or next(iter(results.values()))
+    if do_grad:
+        proc, nevt, seed, precs = GRADIENT
+        gradient = {"workload": f"{proc} {nevt} events seed {seed}: d(w |M|^2)/dr, d log w/dr "
+                                f"({4 * 3} uniforms per event)"}
+        for prec in precs:
+            print(f"[bench] gradient {prec} {nevt} events", file=sys.stderr, flush=True)
+            gradient[prec] = run_gradient(mg, torch, prec, nevt, seed, args.steps, 1,
+                                          cpu.get('gradient', {}).get('results'))
+    plateau = None
+    if do_plateau:
+        proc, nevt, seed, prec = PLATEAU
+        print(f"[bench] plateau {proc} {nevt} events", file=sys.stderr, flush=True)
+        eng, wall, k_ms, nonfinite, scopes, me = run_gpu(mg, torch, proc, prec, seed, nevt,
+                                                         args.steps, args.warmup)
+        plateau = {"workload": f"{proc} {nevt} events seed {seed}", "precision": prec,
+                   "value": nevt * args.steps / wall, "scopes": scopes,
+                   "sigmakin_ms": sum(k_ms) / len(k_ms), "nonfinite": nonfinite}
+        del eng, me
+        torch.cuda.empty_cache()
+
+    cpu_line = None
+    if HEADLINE in cpu:
+        c = cpu[HEADLINE]
+        cpu_line = {"value": c["all_cores"]["value"], "unit": "MEs/s", "cores": cores,
+                    "kind": "oracle", "single_core_value": c["single_core"]["value"],
+                    "cpu": cpu_model(),
+                    "sample": (f"events of the headline workload (seed 3) from {cores} disjoint "
+                               f"ranges: RNG + RAMBO + |M|^2 by the Python/torch FP64 oracle, "
+                               f"{cores} processes x 1 thread for >= {args.cpu_seconds:g} s each "
+                               f"({c['all_cores']['events']} events in "
+                               f"{c['all_cores']['seconds']:.1f} s; start-up excluded)"),
+                    "per_workload": {k: {"single_core": v["single_core"],
+                                         "all_cores": v["all_cores"]}
+                                     for k, v in cpu.items()}}
+    head = variants.get(f"{HEADLINE}_fp64") or (next(iter(variants.values())) if variants else None)
     line = {
         "metric": METRIC,
-        "value": head["value"],
+        "value": head["value"] if head else None,
         "unit": "MEs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": head["ms_per_step"],
+        "ms_per_step": head["ms_per_step"] if head else None,
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": head["value"] / PAPER_V100_GGTTGG if args.process == 'ggttgg' else None,
+        "vs_baseline": (head["value"] / PAPER_V100_GGTTGG
+                        if head and head["workload"].startswith('ggttgg ') else None),
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.process} {args.nevt} events seed {args.seed} "
-                               f"sqrt(s)=1500 GeV (Philox + RAMBO + |M|^2)",
-                   "process": args.process, "nevt": args.nevt, "seed": args.seed,
+        "config": {"workload": head["workload"] + " sqrt(s)=1500 GeV (Philox + RAMBO + |M|^2)"
+                   if head else None,
                    "parallelism": "1 GPU, one event per wave, one helicity per lane"},
-        "roofline": head["roofline"],
-        "cpu_baseline": cpu,
-        "variants": results,
+        "roofline": head["roofline"] if head else None,
+        "vs_oracle": head.get("vs_oracle") if head else None,
+        "cpu_baseline": cpu_line,
+        "variants": variants,
         "gradient": gradient,
+        "plateau": plateau,
     }
     print(json.dumps(line), flush=True)
 
