@@ -50,6 +50,7 @@ extern "C" {
 #define MG_EHIP (-4)     /* HIP runtime or launch error */
 #define MG_EALIGN (-5)   /* buffer not 8-byte aligned */
 #define MG_ENOMEM (-6)   /* mg_create could not allocate its small tables */
+#define MG_ERANGE (-7)   /* size beyond the fixed scratch of an allocation-free entry point */
 
 /* processes (Sec. II, Table "tab-compl"; particle order as written) */
 typedef enum {
@@ -206,6 +207,22 @@ int64_t mg_unweight_workspace_bytes(int64_t n);
  * kernels (count, scan, write) on `stream`. */
 int mg_unweight(const double* f, int64_t n, double fmax, uint64_t seed, int64_t evt_offset,
                 int64_t* idx_out, int64_t* count_out, void* workspace, void* stream);
+
+/* mg_unweight without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same kernels, inputs, outputs and
+ * errors as mg_unweight; the per-block counts live in a fixed device array
+ * of the library (8 bytes per 256 events, 512 KiB, allocated with the
+ * library's code object on each GPU it runs on and held until the process
+ * ends), so n is limited to MG_UNWEIGHT_NOALLOC_MAX_EVENTS (MG_ERANGE
+ * beyond it, before anything is enqueued).  Nothing in that array needs to
+ * start at zero: every call writes the counts it reads.  All calls on one
+ * GPU share the array: calls that overlap in time on one GPU (different
+ * streams, or different host threads without ordering) race and must not
+ * be issued.  Calls no hipMalloc, hipFree or hipMemset. */
+#define MG_UNWEIGHT_NOALLOC_MAX_EVENTS (1 << 24)
+int mg_unweight_noalloc(const double* f, int64_t n, double fmax, uint64_t seed,
+                        int64_t evt_offset, int64_t* idx_out, int64_t* count_out, void* stream);
 
 /* Number of non-finite entries of x[0..n) accumulated into *d_count (a
  * device int64 the caller zeroes first). */

@@ -72,6 +72,7 @@ def lib():
         'mg_xsec_stats': [vp, i64, vp, vp],
         'mg_xsec': [vp, vp, i64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
         'mg_unweight': [vp, i64, ctypes.c_double, u64, i64, vp, vp, vp, vp],
+        'mg_unweight_noalloc': [vp, i64, ctypes.c_double, u64, i64, vp, vp, vp],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)

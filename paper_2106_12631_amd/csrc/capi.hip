@@ -356,6 +356,19 @@ int mg_adjoint(const mg_handle_t* h, const double* rnd, int64_t nevt, const doub
   return hip_status();
 }
 
+int mg_unweight_noalloc(const double* f, int64_t n, double fmax, uint64_t seed,
+                        int64_t evt_offset, int64_t* idx_out, int64_t* count_out, void* stream) {
+  if (n < 0 || evt_offset < 0 || !count_out || (n > 0 && (!f || !idx_out)) || !(fmax >= 0.0))
+    return MG_EINVAL;
+  if (n > MG_UNWEIGHT_NOALLOC_MAX_EVENTS) return MG_ERANGE;
+  if (!aligned8(f) || !aligned8(idx_out) || !aligned8(count_out)) return MG_EALIGN;
+  int64_t* ws = unweight_scratch();
+  if (!ws) return MG_EHIP;
+  if (launch_unweight(f, n, fmax, seed, evt_offset, idx_out, count_out, ws, (hipStream_t)stream))
+    return MG_EINVAL;
+  return hip_status();
+}
+
 int mg_count_nonfinite(const double* x, int64_t n, int64_t* d_count, void* stream) {
   if (n < 0 || !d_count || (n > 0 && !x)) return MG_EINVAL;
   if (!aligned8(x) || !aligned8(d_count)) return MG_EALIGN;
@@ -413,6 +426,7 @@ const char* mg_strerror(int code) {
     case MG_EHIP: return "HIP runtime or kernel launch error";
     case MG_EALIGN: return "buffer not 8-byte aligned";
     case MG_ENOMEM: return "allocation failed";
+    case MG_ERANGE: return "size exceeds the fixed scratch of the allocation-free entry point";
   }
   return "unknown error";
 }

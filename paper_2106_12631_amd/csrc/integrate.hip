@@ -15,6 +15,9 @@
 //   unw_count_kernel   per 256-event block: number kept -> ws[b]
 //   unw_scan_kernel    one block: exclusive prefix sum of ws in place, total
 //   unw_write_kernel   per block: wave ballots + LDS offsets -> idx_out
+#include <mutex>
+
+#include "../../include/mg5mi.h"
 #include "common.h"
 #include "internal.h"
 #include "philox.h"
@@ -127,6 +130,31 @@ __global__ void __launch_bounds__(256) unw_write_kernel(const double* __restrict
   int64_t base = ws[blockIdx.x];
   for (int v = 0; v < w; ++v) base += cnt[v];
   if (k) idx[base + __popcll(m & ((1ull << l) - 1ull))] = i;
+}
+
+// Fixed device scratch of the allocation-free unweighting entry point: one
+// int64 per 256-event block, for at most MG_UNWEIGHT_NOALLOC_MAX_EVENTS
+// events.  Every GPU the library runs on holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in: its
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr int64_t SCRATCH_BLOCKS = (MG_UNWEIGHT_NOALLOC_MAX_EVENTS + 255) / 256;
+static __device__ __align__(256) int64_t scratch[SCRATCH_BLOCKS];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex scratch_mutex;
+static int64_t* scratch_ptr[MAX_DEVICES];
+
+// Device address of `scratch` on the current device (nullptr on error).
+int64_t* unweight_scratch() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    scratch_ptr[dev] = (int64_t*)ptr;
+  }
+  return scratch_ptr[dev];
 }
 
 int launch_xsec_stats(const double* f, int64_t n, double* out, hipStream_t s) {

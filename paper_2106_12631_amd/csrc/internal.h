@@ -38,5 +38,6 @@ int launch_xsec_stats(const double* f, int64_t n, double* out, hipStream_t s);
 int64_t unweight_blocks(int64_t n);
 int launch_unweight(const double* f, int64_t n, double fmax, uint64_t seed, int64_t off,
                     int64_t* idx, int64_t* count, int64_t* ws, hipStream_t s);
+int64_t* unweight_scratch();
 
 }  // namespace mg
