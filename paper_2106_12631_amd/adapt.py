@@ -54,35 +54,37 @@ class WarpMap(torch.nn.Module):
         # output bin widths (ndim, K); `floor` mixes in the uniform map so that
         # no bin is compressed below floor / K (bounds the weights' growth)
         w = (1.0 - self.floor) * torch.softmax(self.logits, dim=-1) + self.floor / K
-        left = torch.cumsum(w, dim=-1) - w                   # output left edges
-        t = u * K
-        k = t.detach().floor().clamp(0, K - 1).long()        # input bin per (event, dim)
-        frac = t - k
-        dims = torch.arange(self.ndim, device=u.device).expand_as(k)
-        wk = w[dims, k]
-        x = left[dims, k] + frac * wk
+        x, d = _pwl(u, w.unsqueeze(0))
         tiny = torch.finfo(u.dtype).eps
-        x = x.clamp(tiny, 1.0 - tiny)
-        jac = (K * wk).prod(dim=-1)
-        return x, jac
+        return x.clamp(tiny, 1.0 - tiny), d.prod(dim=-1)
 
     def inverse(self, x):
         """u = g^-1(x) and the Jacobian |dg/du| at u."""
         K = self.nbins
         w = (1.0 - self.floor) * torch.softmax(self.logits, dim=-1) + self.floor / K
-        u, d = _pwl_inverse(x, w.unsqueeze(0).expand(x.shape[0], -1, -1))
+        u, d = _pwl_inverse(x, w.unsqueeze(0))
         return u, d.prod(dim=-1)
 
 
+def _onehot(k, K, dtype):
+    return (k.unsqueeze(-1) == torch.arange(K, device=k.device)).to(dtype)
+
+
+# The bin lookups below select with one-hot masks and sums instead of
+# gather / advanced indexing: the backward pass of those scatters into the
+# widths with atomic additions on the device, whose order (and so the
+# rounding of the trained map) changes from run to run.  Masked sums reduce
+# in a fixed order, so training is reproducible bit for bit.
 def _pwl(u, w):
     """Monotone piecewise-linear map of (0, 1) with equal input bins and
     output bin widths w (..., K), summing to 1: x and dx/du per entry."""
     K = w.shape[-1]
     t = u * K
-    k = t.detach().floor().clamp(0, K - 1).long().unsqueeze(-1)
+    k = t.detach().floor().clamp(0, K - 1)
+    oh = _onehot(k.long(), K, w.dtype)
     left = torch.cumsum(w, dim=-1) - w
-    wk = torch.gather(w, -1, k).squeeze(-1)
-    x = torch.gather(left, -1, k).squeeze(-1) + (t - k.squeeze(-1)) * wk
+    wk = (oh * w).sum(-1)
+    x = (oh * left).sum(-1) + (t - k) * wk
     return x, K * wk
 
 
@@ -90,11 +92,12 @@ def _pwl_inverse(x, w):
     """Inverse of _pwl: u with _pwl(u, w) = x, and dx/du at u."""
     K = w.shape[-1]
     right = torch.cumsum(w, dim=-1)
-    k = torch.searchsorted(right.detach().contiguous(), x.detach().unsqueeze(-1).contiguous(),
-                           right=True).clamp(0, K - 1)
-    wk = torch.gather(w, -1, k).squeeze(-1)
-    left = torch.gather(right - w, -1, k).squeeze(-1)
-    u = (k.squeeze(-1) + (x - left) / wk) / K
+    # the output bin of x: the number of right edges at or below x
+    k = (right.detach() <= x.detach().unsqueeze(-1)).sum(-1).clamp(0, K - 1)
+    oh = _onehot(k, K, w.dtype)
+    wk = (oh * w).sum(-1)
+    left = (oh * (right - w)).sum(-1)
+    u = (k.to(x.dtype) + (x - left) / wk) / K
     return u, K * wk
 
 
