@@ -15,8 +15,8 @@
  *   - `stream` is a hipStream_t cast to void* (NULL = the null stream).
  *     Calls enqueue work on it and return without synchronising, except
  *     mg_create (which allocates, runs and frees a small helicity-filtering
- *     pass and waits for it); mg_xsec and mg_unweight_workspace_bytes are
- *     host arithmetic only.
+ *     pass and waits for it); mg_xsec and the *_workspace_bytes functions
+ *     are host arithmetic only.
  *   - A handle is immutable after mg_create; any number of streams may use
  *     it concurrently with disjoint outputs.
  *
@@ -178,10 +178,14 @@ int mg_adjoint(const mg_handle_t* h, const double* rnd, int64_t nevt, const doub
 /* Cross-section statistics of n weighted events f = w |M|^2 (device FP64,
  * e.g. evtw from mg_sigmakin): stats[0] = sum of the finite f, stats[1] =
  * sum of their squares, stats[2] = their maximum (0 if none), stats[3] =
- * how many are finite; stats is a device array of 4 doubles.  One block of
- * 1024 threads in a fixed summation order, so the result does not depend on
- * timing (Sec. II: cross section from weighted events). */
-int mg_xsec_stats(const double* f, int64_t n, double* stats, void* stream);
+ * how many are finite; stats is a device array of 4 doubles.  Two kernels
+ * of fixed shape (blocks over contiguous event ranges, then one block over
+ * their partial sums) in a fixed summation order, so the result does not
+ * depend on timing (Sec. II: cross section from weighted events).
+ * workspace: device memory of mg_xsec_stats_workspace_bytes(n) bytes
+ * (8-byte aligned, contents need not be initialised; at most 64 KiB). */
+int64_t mg_xsec_stats_workspace_bytes(int64_t n);
+int mg_xsec_stats(const double* f, int64_t n, double* stats, void* workspace, void* stream);
 
 /* Host: cross section and Monte Carlo error in pb from stats copied to the
  * host, for n events of h's process:

@@ -69,7 +69,7 @@ def lib():
         'mg_sigmakin_hel': [vp, vp, i64, vp, vp],
         'mg_count_nonfinite': [vp, i64, vp, vp],
         'mg_adjoint': [vp, vp, i64, vp, vp, vp, vp, vp],
-        'mg_xsec_stats': [vp, i64, vp, vp],
+        'mg_xsec_stats': [vp, i64, vp, vp, vp],
         'mg_xsec': [vp, vp, i64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
         'mg_unweight': [vp, i64, ctypes.c_double, u64, i64, vp, vp, vp, vp],
         'mg_unweight_noalloc': [vp, i64, ctypes.c_double, u64, i64, vp, vp, vp],
@@ -78,8 +78,9 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = ci
-    L.mg_unweight_workspace_bytes.argtypes = [i64]
-    L.mg_unweight_workspace_bytes.restype = i64
+    for name in ('mg_unweight_workspace_bytes', 'mg_xsec_stats_workspace_bytes'):
+        getattr(L, name).argtypes = [i64]
+        getattr(L, name).restype = i64
     L.mg_strerror.argtypes = [ci]
     L.mg_strerror.restype = ctypes.c_char_p
     _LIB = L
@@ -300,7 +301,10 @@ def xsec_stats(f):
     """Device tensor (4,) = (sum, sum of squares, max, count) of the finite f."""
     f = f.contiguous()
     out = torch.empty(4, dtype=torch.float64, device=f.device)
-    _check(lib().mg_xsec_stats(_ptr(f), f.numel(), _ptr(out), _stream(f.device)), 'mg_xsec_stats')
+    nb = lib().mg_xsec_stats_workspace_bytes(f.numel())
+    ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=f.device)
+    _check(lib().mg_xsec_stats(_ptr(f), f.numel(), _ptr(out), _ptr(ws), _stream(f.device)),
+           'mg_xsec_stats')
     return out
 
 

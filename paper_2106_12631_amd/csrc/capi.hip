@@ -377,10 +377,14 @@ int mg_count_nonfinite(const double* x, int64_t n, int64_t* d_count, void* strea
   return hip_status();
 }
 
-int mg_xsec_stats(const double* f, int64_t n, double* stats, void* stream) {
-  if (n < 0 || !stats || (n > 0 && !f)) return MG_EINVAL;
-  if (!aligned8(f) || !aligned8(stats)) return MG_EALIGN;
-  launch_xsec_stats(f, n, stats, (hipStream_t)stream);
+int64_t mg_xsec_stats_workspace_bytes(int64_t n) {
+  return xsec_blocks(n < 0 ? 0 : n) * 4 * (int64_t)sizeof(double);
+}
+
+int mg_xsec_stats(const double* f, int64_t n, double* stats, void* workspace, void* stream) {
+  if (n < 0 || !stats || !workspace || (n > 0 && !f)) return MG_EINVAL;
+  if (!aligned8(f) || !aligned8(stats) || !aligned8(workspace)) return MG_EALIGN;
+  launch_xsec_stats(f, n, stats, (double*)workspace, (hipStream_t)stream);
   return hip_status();
 }
 

@@ -3,10 +3,10 @@
 // section and a sample of unweighted events obtained from a larger set of
 // weighted ones by Monte Carlo).
 //
-// xsec_stats_kernel: one block of 1024 threads; thread t sums a contiguous
-// chunk of events in FP64 (sum f, sum f^2, max f, number of finite f), then a
-// fixed-order tree over the block: the result does not depend on timing.
-// Non-finite f are left out and counted.
+// xsec_partial_kernel + xsec_final_kernel: FP64 sums of f and f^2, the
+// maximum and the number of finite f in two passes of fixed shape (blocks
+// over contiguous event ranges, then one block over their partials), so the
+// result does not depend on timing.  Non-finite f are left out.
 //
 // Hit-or-miss unweighting: event i is kept iff u_i fmax < f_i with u_i the
 // Philox uniform of (seed, event evt_offset + i) at block UNW_BLOCK (a
@@ -32,14 +32,44 @@ __device__ __forceinline__ double unweight_uniform(uint64_t seed, uint64_t ievt)
   return bits_to_u(c0, c1);
 }
 
-__global__ void __launch_bounds__(1024) xsec_stats_kernel(const double* __restrict__ f, int64_t n,
-                                                          double* __restrict__ out) {
-  __shared__ double s0[1024], s1[1024], s2[1024], s3[1024];
+// Deterministic two-pass reduction of (sum f, sum f^2, max f, finite count).
+// Pass 1: block b reduces the contiguous event range [b*chunk, (b+1)*chunk)
+// (coalesced: thread t reads events b*chunk + t + 256 k), then a fixed tree
+// over its 256 threads -> ws[4b .. 4b+3].  Pass 2: one block of 1024 threads
+// reduces the nb partials (thread t: partials t, t + 1024, ...) by a fixed
+// tree.  The block count and ranges depend on n only, so the result does not
+// depend on timing.
+constexpr int XS_THREADS = 256;
+constexpr int64_t XS_MAX_BLOCKS = 2048;
+constexpr int64_t XS_MIN_CHUNK = 4096;
+
+int64_t xsec_blocks(int64_t n) {
+  int64_t nb = (n + XS_MIN_CHUNK - 1) / XS_MIN_CHUNK;
+  return nb < 1 ? 1 : (nb > XS_MAX_BLOCKS ? XS_MAX_BLOCKS : nb);
+}
+
+template <int NT>
+__device__ __forceinline__ void reduce4(double (&s)[4][NT], int t) {
+  for (int st = NT / 2; st > 0; st >>= 1) {
+    if (t < st) {
+      s[0][t] += s[0][t + st];
+      s[1][t] += s[1][t + st];
+      s[2][t] = s[2][t + st] > s[2][t] ? s[2][t + st] : s[2][t];
+      s[3][t] += s[3][t + st];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(XS_THREADS) xsec_partial_kernel(const double* __restrict__ f,
+                                                                  int64_t n, int64_t chunk,
+                                                                  double* __restrict__ ws) {
+  __shared__ double s[4][XS_THREADS];
   const int t = threadIdx.x;
-  const int64_t chunk = (n + 1023) / 1024;
-  const int64_t b = (int64_t)t * chunk, e = b + chunk < n ? b + chunk : n;
+  const int64_t b = (int64_t)blockIdx.x * chunk;
+  const int64_t e = b + chunk < n ? b + chunk : n;
   double sum = 0.0, sq = 0.0, mx = 0.0, cnt = 0.0;
-  for (int64_t i = b; i < e; ++i) {
+  for (int64_t i = b + t; i < e; i += XS_THREADS) {
     const double v = f[i];
     if (isfinite(v)) {
       sum += v;
@@ -48,26 +78,33 @@ __global__ void __launch_bounds__(1024) xsec_stats_kernel(const double* __restri
       cnt += 1.0;
     }
   }
-  s0[t] = sum;
-  s1[t] = sq;
-  s2[t] = mx;
-  s3[t] = cnt;
+  s[0][t] = sum;
+  s[1][t] = sq;
+  s[2][t] = mx;
+  s[3][t] = cnt;
   __syncthreads();
-  for (int st = 512; st > 0; st >>= 1) {
-    if (t < st) {
-      s0[t] += s0[t + st];
-      s1[t] += s1[t + st];
-      s2[t] = s2[t + st] > s2[t] ? s2[t + st] : s2[t];
-      s3[t] += s3[t + st];
-    }
-    __syncthreads();
+  reduce4<XS_THREADS>(s, t);
+  if (t < 4) ws[4 * blockIdx.x + t] = s[t][0];
+}
+
+__global__ void __launch_bounds__(1024) xsec_final_kernel(const double* __restrict__ ws,
+                                                          int64_t nb, double* __restrict__ out) {
+  __shared__ double s[4][1024];
+  const int t = threadIdx.x;
+  double sum = 0.0, sq = 0.0, mx = 0.0, cnt = 0.0;
+  for (int64_t k = t; k < nb; k += 1024) {
+    sum += ws[4 * k];
+    sq += ws[4 * k + 1];
+    mx = ws[4 * k + 2] > mx ? ws[4 * k + 2] : mx;
+    cnt += ws[4 * k + 3];
   }
-  if (t == 0) {
-    out[0] = s0[0];
-    out[1] = s1[0];
-    out[2] = s2[0];
-    out[3] = s3[0];
-  }
+  s[0][t] = sum;
+  s[1][t] = sq;
+  s[2][t] = mx;
+  s[3][t] = cnt;
+  __syncthreads();
+  reduce4<1024>(s, t);
+  if (t < 4) out[t] = s[t][0];
 }
 
 __device__ __forceinline__ bool keep(const double* f, int64_t i, int64_t n, double fmax,
@@ -157,8 +194,11 @@ int64_t* unweight_scratch() {
   return scratch_ptr[dev];
 }
 
-int launch_xsec_stats(const double* f, int64_t n, double* out, hipStream_t s) {
-  xsec_stats_kernel<<<1, 1024, 0, s>>>(f, n, out);
+int launch_xsec_stats(const double* f, int64_t n, double* out, double* ws, hipStream_t s) {
+  const int64_t nb = xsec_blocks(n);
+  const int64_t chunk = n > 0 ? (n + nb - 1) / nb : 0;
+  xsec_partial_kernel<<<(unsigned)nb, XS_THREADS, 0, s>>>(f, n, chunk, ws);
+  xsec_final_kernel<<<1, 1024, 0, s>>>(ws, nb, out);
   return 0;
 }
 

@@ -34,7 +34,8 @@ int launch_sigmakin(int proc, int prec, const MeArgs& a, const double* mom, int6
 int launch_sigmakin_hel(int proc, int prec, const MeArgs& a, const double* mom, int64_t nevt,
                         double* mehel, hipStream_t s);
 int launch_count_nonfinite(const double* x, int64_t n, int64_t* d_count, hipStream_t s);
-int launch_xsec_stats(const double* f, int64_t n, double* out, hipStream_t s);
+int64_t xsec_blocks(int64_t n);
+int launch_xsec_stats(const double* f, int64_t n, double* out, double* ws, hipStream_t s);
 int64_t unweight_blocks(int64_t n);
 int launch_unweight(const double* f, int64_t n, double fmax, uint64_t seed, int64_t off,
                     int64_t* idx, int64_t* count, int64_t* ws, hipStream_t s);

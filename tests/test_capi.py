@@ -20,8 +20,8 @@ def test_header_declares_the_path():
     names = set(declared())
     assert {'mg_create', 'mg_destroy', 'mg_layout', 'mg_rng', 'mg_rambo', 'mg_sample',
             'mg_sigmakin', 'mg_sigmakin_hel', 'mg_adjoint', 'mg_count_nonfinite', 'mg_strerror',
-            'mg_xsec_stats', 'mg_xsec', 'mg_unweight', 'mg_unweight_workspace_bytes',
-            'mg_unweight_noalloc'} <= names
+            'mg_xsec_stats', 'mg_xsec_stats_workspace_bytes', 'mg_xsec', 'mg_unweight',
+            'mg_unweight_workspace_bytes', 'mg_unweight_noalloc'} <= names
 
 
 @pytest.mark.skipif(not os.path.exists(LIBPATH), reason="library not built")

@@ -1,7 +1,8 @@
 """Cross section and unweighting kernels against the oracle (GPU).
 
 * mg_xsec_stats: sums within 1e-13 relative of the oracle's (a different
-  summation order), maximum and finite count exact;
+  summation order), maximum and finite count exact, the same bits on a
+  second call (fixed summation order), up to 2^24 + 3 events;
 * mg_unweight: the kept index list is identical to the oracle's (an integer
   result decided by the same FP64 comparison on the same uniforms);
 * inputs are seeded synthetic weights (heavy-tailed, with NaN and infinite
@@ -48,7 +49,7 @@ def weights(n, seed, special=True):
     return f
 
 
-@pytest.mark.parametrize('n', [0, 1, 255, 256, 257, 4096 + 37, 1 << 20])
+@pytest.mark.parametrize('n', [0, 1, 255, 256, 257, 4096 + 37, 1 << 20, (1 << 24) + 3])
 def test_xsec_stats(mg, n):
     f = weights(n, 100 + n)
     say('xsec_stats', n)
@@ -57,6 +58,9 @@ def test_xsec_stats(mg, n):
     for k in (0, 1):
         assert st[k] == pytest.approx(ref[k], rel=1e-13, abs=0.0)
     assert st[2] == ref[2] and st[3] == ref[3]
+    # fixed summation order: a second call gives the same bits
+    st2 = mg.xsec_stats(torch.from_numpy(f).cuda()).cpu().numpy()
+    assert np.array_equal(st, st2)
 
 
 @pytest.mark.parametrize('n,fmax,seed,off', [(0, 1.0, 1, 0), (1, 0.5, 2, 0), (255, 2.0, 3, 7),
@@ -74,7 +78,13 @@ def test_unweight_bitexact(mg, n, fmax, seed, off):
 
 def test_errors(mg):
     L = mg.lib()
-    assert L.mg_xsec_stats(None, 4, None, None) == -1
+    assert L.mg_xsec_stats(None, 4, None, None, None) == -1
+    ws = torch.empty(L.mg_xsec_stats_workspace_bytes(1 << 30) // 8, dtype=torch.float64).cuda()
+    out = torch.empty(4, dtype=torch.float64).cuda()
+    assert L.mg_xsec_stats(None, 4, out.data_ptr(), ws.data_ptr(), None) == -1
+    assert L.mg_xsec_stats(out.data_ptr(), 4, out.data_ptr(), None, None) == -1
+    assert L.mg_xsec_stats_workspace_bytes(0) == 32
+    assert L.mg_xsec_stats_workspace_bytes(1 << 30) == 2048 * 32
     assert L.mg_unweight(None, 4, 1.0, 0, 0, None, None, None, None) == -1
     f = torch.ones(4, dtype=torch.float64).cuda()
     assert L.mg_unweight(f.data_ptr(), 4, -1.0, 0, 0, f.data_ptr(), f.data_ptr(), f.data_ptr(),
