@@ -362,6 +362,8 @@ def main():
                     help='minimum oracle time per workload, on 1 core and on all cores')
     ap.add_argument('--no-gradient', action='store_true')
     ap.add_argument('--no-plateau', action='store_true')
+    ap.add_argument('--no-calibration', action='store_true',
+                    help='skip the arithmetic-peak calibration kernels')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='only run a plain 1 GiB device-to-device copy (HBM counter calibration)')
     args = ap.parse_args()
@@ -394,6 +396,11 @@ def main():
     import paper_2106_12631_amd as mg
     metas = json.load(open(os.path.join(ROOT, 'paper_2106_12631_amd', 'csrc', 'generated',
                                         'meta.json')))
+    calibration = None
+    if not args.no_calibration:
+        from paper_2106_12631_amd import calibrate
+        print("[bench] calibration kernels", file=sys.stderr, flush=True)
+        calibration = calibrate.run()
     variants = {}
     for name, proc, nevt, seed, precs in workloads:
         meta = metas[proc]
@@ -484,6 +491,7 @@ def main():
         "roofline": head["roofline"] if head else None,
         "vs_oracle": head.get("vs_oracle") if head else None,
         "cpu_baseline": cpu_line,
+        "calibration": calibration,
         "variants": variants,
         "gradient": gradient,
         "plateau": plateau,

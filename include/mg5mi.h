@@ -70,7 +70,16 @@ typedef enum {
  *               with FP32 accumulation: for 24 colour flows (g g -> t t~ g g)
  *               the jamps are split into three BF16 terms against the exact
  *               BF16 colour numerators; otherwise FP32 MFMA operands
- *   MG_MIXED_F32MFMA  as MG_MIXED with FP32 MFMA operands for every process */
+ *   MG_MIXED_F32MFMA  as MG_MIXED with FP32 MFMA operands for every process
+ * Precision guard (the three reduced-precision forms, unless
+ * MG_FLAG_NO_PRECISION_GUARD): |M|^2 is ill-conditioned in its invariants
+ * when kappa = s / min_{i<j} |2 p_i.p_j| over the external momenta is large
+ * (soft or collinear gluons), where FP32 rounding of the diagram sums grows
+ * like eps32 sqrt(kappa).  After the reduced-precision kernel, the events
+ * with kappa > MG_PRECISION_GUARD_KAPPA are recomputed in FP64 (one more
+ * kernel on the same stream; about 0.04 % of g g -> t t~ g and 0.2 % of
+ * g g -> t t~ g g benchmark events). */
+#define MG_PRECISION_GUARD_KAPPA 1.0e4
 typedef enum { MG_FP64 = 0, MG_FP32AMP = 1, MG_MIXED = 2, MG_MIXED_F32MFMA = 3 } mg_prec_t;
 
 /* bits of mg_params_t.flags (Sec. IV.c: physics parameters of the kernels;
@@ -81,9 +90,12 @@ typedef enum { MG_FP64 = 0, MG_FP32AMP = 1, MG_MIXED = 2, MG_MIXED_F32MFMA = 3 }
  *       at O(wt); by default every top propagator carries wt.
  *   MG_FLAG_WEIGHT_2PI  RAMBO weights carry (2 pi)^(4 - 3 nfinal), i.e. the
  *       measure prod d^3p/((2 pi)^3 2E) (2 pi)^4 delta^4; mg_xsec then adds
- *       no 2 pi factor of its own. */
+ *       no 2 pi factor of its own.
+ *   MG_FLAG_NO_PRECISION_GUARD  turn off the precision guard of the
+ *       reduced-precision forms (see mg_prec_t). */
 #define MG_FLAG_TCHANNEL_ZERO_WIDTH 1
 #define MG_FLAG_WEIGHT_2PI 2
+#define MG_FLAG_NO_PRECISION_GUARD 4
 
 /* physics inputs; couplings are derived in mg_create (sin^2 theta_W in the
  * G_F scheme from alpha, G_F and mZ) */

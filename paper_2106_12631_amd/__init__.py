@@ -29,6 +29,7 @@ class Params(ctypes.Structure):
 # bits of Params.flags (include/mg5mi.h)
 FLAG_TCHANNEL_ZERO_WIDTH = 1
 FLAG_WEIGHT_2PI = 2
+FLAG_NO_PRECISION_GUARD = 4
 
 DEFAULT_PARAMS = dict(sqrts=1500.0, alpha_inv=132.5, gfermi=1.16639e-5, mZ=91.188, wZ=2.441,
                       mt=173.0, wt=1.49, alphas=0.118, flags=0)

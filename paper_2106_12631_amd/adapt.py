@@ -188,25 +188,6 @@ def relative_second_moment(F):
     return (F * F).mean() / (m * m)
 
 
-def kl_divergence(F):
-    """KL(p || q) up to a constant for the target density p = f / I and the
-    sampling density q = 1 / |dg/du| of the map: E_u[(F/I) log(F/I)] with
-    I estimated by the batch mean (held fixed in the gradient)."""
-    r = F / F.mean().detach()
-    return (r * torch.log(r.clamp_min(1e-300))).mean()
-
-
-def log_variance(F):
-    """Variance of log F over the points with F > 0 (cut points carry no
-    information on log F): zero at the optimum like the relative variance,
-    far less sensitive to the rare large weights of a heavy-tailed sample."""
-    lf = torch.log(F[F > 0])
-    return ((lf - lf.mean()) ** 2).mean()
-
-
-LOSSES = {'variance': relative_second_moment, 'kl': kl_divergence, 'logvar': log_variance}
-
-
 def estimate(F):
     """Mean, its standard error and the relative variance of a weight sample."""
     n = F.numel()
@@ -234,13 +215,12 @@ def sample_weights(m, fn, u, mix=0.0):
 
 
 def train(fn, ndim, uniforms, iters=200, batch=1 << 14, nbins=32, lr=0.05, device=None,
-          log=None, clip=0.995, loss='variance', floor=0.0, flow='warp', mix=0.0):
-    """Train a WarpMap for the integrand fn (a differentiable torch function
+          log=None, clip=0.995, floor=0.0, flow='warp', mix=0.0):
+    """Train a map for the integrand fn (a differentiable torch function
     of (N, ndim) points in (0, 1) returning (N,) weights); uniforms(i, n)
-    returns the i-th batch of n uniforms.  loss: 'variance' (relative second
-    moment E[F^2]/E[F]^2), 'kl' (KL divergence of the sampling density from
-    the integrand) or 'logvar' (variance of log F), each on weights capped at
-    the batch's `clip` quantile; floor: see WarpMap; flow: 'warp'
+    returns the i-th batch of n uniforms.  The loss is the relative second
+    moment E[F^2]/E[F]^2 of the weights capped at the batch's `clip`
+    quantile; floor: see WarpMap; flow: 'warp'
     (WarpMap) or 'coupling' (CouplingFlow); mix: the flat share of the
     defensive mixture (see sample_weights), trained as it is evaluated.
     Returns the map and the loss history."""
@@ -253,20 +233,19 @@ def train(fn, ndim, uniforms, iters=200, batch=1 << 14, nbins=32, lr=0.05, devic
         # the weights are heavy-tailed: the training loss caps them at the
         # batch's `clip` quantile (the estimates always use the raw weights)
         cap = torch.quantile(F.detach(), clip) if clip < 1.0 else None
-        value = LOSSES[loss](torch.minimum(F, cap) if cap is not None else F)
+        value = relative_second_moment(torch.minimum(F, cap) if cap is not None else F)
         opt.zero_grad()
         value.backward()
         torch.nn.utils.clip_grad_norm_(m.parameters(), 1.0)
         opt.step()
         hist.append(float(value.detach()))
         if log and (it % max(1, iters // 10) == 0 or it == iters - 1):
-            log(f"iter {it} {loss} loss {hist[-1]:.4g}")
+            log(f"iter {it} variance loss {hist[-1]:.4g}")
     return m, hist
 
 
 def adapt_process(engine, seed=4, iters=200, batch=1 << 14, nbins=32, lr=0.05, eval_batch=1 << 18,
-                  log=None, cut=None, clip=0.995, loss='variance', floor=0.0, flow='warp',
-                  mix=0.0):
+                  log=None, cut=None, clip=0.995, floor=0.0, flow='warp', mix=0.0):
     """Adapt the uniforms of engine's process and compare with flat sampling.
 
     cut: None or a function r -> (N,) indicator (see pt_cut) multiplying
@@ -284,7 +263,7 @@ def adapt_process(engine, seed=4, iters=200, batch=1 << 14, nbins=32, lr=0.05, e
         return f if cut is None else f * cut(x)
 
     m, hist = train(fn, nr, uniforms, iters, batch, nbins, lr, device=engine.device, log=log,
-                    clip=clip, loss=loss, floor=floor, flow=flow, mix=mix)
+                    clip=clip, floor=floor, flow=flow, mix=mix)
     with torch.no_grad():
         u = uniforms(0, eval_batch, seed + 1)
         flat = fn(u)

@@ -2,7 +2,11 @@
 
 Steps: run the diagram generator (gen/) to emit csrc/generated/*.inc, compile
 every csrc/*.hip with hipcc for gfx950, link one shared library next to this
-file.  Usage: python -m paper_2106_12631_amd.build [--force]
+file; then build the calibration kernels (calib/) as libmg5cal.so.
+
+    python -m paper_2106_12631_amd.build               build both libraries
+    python -m paper_2106_12631_amd.build --resources   print the compiler's
+        register, scratch, LDS and occupancy report of every kernel
 """
 import os
 import subprocess
@@ -24,10 +28,10 @@ FLAGS = [
     '-I', CSRC, '-I', INCLUDE,
 ]
 
-# Flags of single sources.  The helicity-per-lane mixed kernel calls its
-# matrix-core colour sum out of line; with the MFMA results in VGPRs and the
-# callee's saved registers on the stack instead of in AGPRs it needs no AGPRs
-# and runs two waves per SIMD.
+# Flags of single sources.  The helicity-per-lane mixed kernel runs its
+# matrix-core colour sum after the FP32 amplitudes; with the MFMA results in
+# VGPRs and no VGPR spills to AGPRs it needs no AGPRs and keeps two waves per
+# SIMD.
 SOURCE_FLAGS = {
     'sigmakin_ggttgg_mixed.hip': ['-mllvm', '-amdgpu-mfma-vgpr-form',
                                   '-mllvm', '-amdgpu-spill-vgpr-to-agpr=0'],
@@ -70,10 +74,55 @@ def build(force=True, verbose=True, extra_flags=(), output=None):
     tmp = lib + '.tmp'
     subprocess.check_call([HIPCC, '--offload-arch=gfx950', '-shared', '-fPIC', '-o', tmp, *objs])
     os.replace(tmp, lib)
+    if output is None:
+        # the calibration kernels (arithmetic peaks), a library of their own
+        cal = os.path.join(HERE, 'libmg5cal.so')
+        subprocess.check_call([HIPCC, *FLAGS, '-shared', '-o', cal + '.tmp',
+                               os.path.join(HERE, 'calib', 'calibrate.hip')],
+                              stderr=subprocess.DEVNULL)
+        os.replace(cal + '.tmp', cal)
     if verbose:
         print(f"[build] {lib} in {time.time() - t0:.1f}s", file=sys.stderr)
     return lib
 
 
+def resource_report():
+    """Markdown table of every kernel's registers, scratch, LDS and
+    occupancy as the compiler reports them for gfx950
+    (-Rpass-analysis=kernel-resource-usage), one row per kernel."""
+    import re
+    rows = []
+    for src in sources():
+        cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, ()), '-Rpass-analysis=kernel-resource-usage',
+               '-c', os.path.join(CSRC, src), '-o', os.devnull]
+        out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                             text=True).stdout
+        cur = None
+        for line in out.splitlines():
+            m = re.search(r'remark:\s+(Function Name|TotalSGPRs|VGPRs|AGPRs|ScratchSize \[bytes/lane\]|'
+                          r'Occupancy \[waves/SIMD\]|LDS Size \[bytes/block\]):\s*(\S+)', line)
+            if not m:
+                continue
+            key, val = m.group(1).split(' [')[0], m.group(2)
+            if key == 'Function Name':
+                cur = {'source': src, 'kernel': val}
+                rows.append(cur)
+            elif cur is not None:
+                cur[key] = val
+    demangled = subprocess.run(['c++filt'], input='\n'.join(r['kernel'] for r in rows),
+                               stdout=subprocess.PIPE, text=True).stdout.splitlines()
+    lines = ['| source | kernel | VGPRs | AGPRs | SGPRs | scratch B/lane | LDS B/block | waves/SIMD |',
+             '|---|---|---|---|---|---|---|---|']
+    for r, d in zip(rows, demangled):
+        name = re.sub(r'\(.*$', '', d).replace('mg::', '')
+        lines.append(f"| {r['source']} | `{name}` | {r.get('VGPRs')} | {r.get('AGPRs')} | "
+                     f"{r.get('TotalSGPRs')} | {r.get('ScratchSize')} | {r.get('LDS Size')} | "
+                     f"{r.get('Occupancy')} |")
+    return '\n'.join(lines)
+
+
 if __name__ == '__main__':
-    build()
+    if '--resources' in sys.argv:
+        print(resource_report())
+    else:
+        build()

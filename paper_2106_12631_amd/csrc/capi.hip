@@ -48,14 +48,34 @@ static const sk_fn SK[4][2] = {
     {launch_sigmakin_ggttgg_f64, launch_sigmakin_ggttgg_f32},
 };
 
+#define MG_DECL(p)                                                                          \
+  int launch_sigmakin_##p##_guard(const MeArgs&, const double*, int64_t, double*, const double*, \
+                                  double*, hipStream_t);
+MG_DECL(eemumu)
+MG_DECL(ggtt)
+MG_DECL(ggttg)
+MG_DECL(ggttgg)
+#undef MG_DECL
+static const skm_fn GUARD[4] = {launch_sigmakin_eemumu_guard, launch_sigmakin_ggtt_guard,
+                                launch_sigmakin_ggttg_guard, launch_sigmakin_ggttgg_guard};
+
 // prec: 0 FP64, 1 FP32 amplitudes + VALU colour sum, 2 mixed (BF16-split MFMA
-// colour sum for 24 colour flows, FP32 MFMA otherwise), 3 mixed with FP32 MFMA
+// colour sum for 24 colour flows, FP32 MFMA otherwise), 3 mixed with FP32 MFMA;
+// the reduced-precision forms are followed by the precision guard (FP64 for
+// the ill-conditioned events) when a.guard_kappa > 0
 int launch_sigmakin(int proc, int prec, const MeArgs& a, const double* mom, int64_t nevt,
                     double* me, const double* wgt, double* evtw, hipStream_t s) {
   if (proc < 0 || proc > 3 || prec < 0 || prec > 3) return -1;
-  if (prec <= 1) return SK[proc][prec](a, mom, nevt, me, wgt, evtw, nullptr, s);
-  const int bf16 = (prec == 2 && proc == MG_GGTTGG) ? 1 : 0;
-  return SKM[proc][bf16](a, mom, nevt, me, wgt, evtw, s);
+  int rc;
+  if (prec == 0) return SK[proc][0](a, mom, nevt, me, wgt, evtw, nullptr, s);
+  if (prec == 1) {
+    rc = SK[proc][1](a, mom, nevt, me, wgt, evtw, nullptr, s);
+  } else {
+    const int bf16 = (prec == 2 && proc == MG_GGTTGG) ? 1 : 0;
+    rc = SKM[proc][bf16](a, mom, nevt, me, wgt, evtw, s);
+  }
+  if (rc) return rc;
+  return GUARD[proc](a, mom, nevt, me, wgt, evtw, s);
 }
 
 int launch_sigmakin_hel(int proc, int prec, const MeArgs& a, const double* mom, int64_t nevt,
@@ -162,6 +182,8 @@ static void derive(mg_handle* h) {
   f.wz = c.wz;
   h->me.c32 = f;
   h->me.inv_iden = 1.0 / PROC_INFO[h->proc].iden;
+  h->me.guard_kappa =
+      (h->prec != MG_FP64 && !(p.flags & MG_FLAG_NO_PRECISION_GUARD)) ? MG_PRECISION_GUARD_KAPPA : 0.0;
 
   const int nf = PROC_INFO[h->proc].npar - 2;
   RamboArgs& r = h->rambo;
@@ -233,7 +255,7 @@ int mg_create(int proc, int prec, const mg_params_t* prm, mg_handle_t** out) {
   if (prm) p = *prm;
   if (!(p.sqrts > 0) || !(p.alpha_inv > 0) || !(p.gfermi > 0) || !(p.mZ > 0) || p.wZ < 0 ||
       p.mt < 0 || p.wt < 0 || !(p.alphas > 0) ||
-      (p.flags & ~(MG_FLAG_TCHANNEL_ZERO_WIDTH | MG_FLAG_WEIGHT_2PI)) != 0)
+      (p.flags & ~(MG_FLAG_TCHANNEL_ZERO_WIDTH | MG_FLAG_WEIGHT_2PI | MG_FLAG_NO_PRECISION_GUARD)) != 0)
     return MG_EINVAL;
   if (proc != MG_EEMUMU && 2.0 * p.mt >= p.sqrts) return MG_ENOPHASE;
   mg_handle* h = new (std::nothrow) mg_handle();

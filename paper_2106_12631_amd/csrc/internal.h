@@ -27,6 +27,7 @@ struct MeArgs {
   Couplings<float> c32;
   HelList hel;
   double inv_iden;
+  double guard_kappa;  // reduced precision: FP64 recomputation above this kappa (0: off)
 };
 
 int launch_sigmakin(int proc, int prec, const MeArgs& a, const double* mom, int64_t nevt,

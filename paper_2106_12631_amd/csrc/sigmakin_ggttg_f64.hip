@@ -26,4 +26,11 @@ int launch_sigmakin_ggttg_f64(const MeArgs& a, const double* mom, int64_t nevt, 
   return sigmakin_launch<P_ggttg, double, MG_EPL_BLOCK>(a, a.c64, mom, nevt, me, wgt, evtw, mehel, s);
 }
 
+// FP64 recomputation of the ill-conditioned events of a reduced-precision
+// launch (precision guard of sigmakin_impl.h)
+int launch_sigmakin_ggttg_guard(const MeArgs& a, const double* mom, int64_t nevt, double* me,
+                              const double* wgt, double* evtw, hipStream_t s) {
+  return sigmakin_guard_launch<P_ggttg>(a, mom, nevt, me, wgt, evtw, s);
+}
+
 }  // namespace mg

@@ -30,4 +30,11 @@ int launch_sigmakin_ggttgg_f64(const MeArgs& a, const double* mom, int64_t nevt,
 #endif
 }
 
+// FP64 recomputation of the ill-conditioned events of a reduced-precision
+// launch (precision guard of sigmakin_impl.h)
+int launch_sigmakin_ggttgg_guard(const MeArgs& a, const double* mom, int64_t nevt, double* me,
+                              const double* wgt, double* evtw, hipStream_t s) {
+  return sigmakin_guard_launch<P_ggttgg>(a, mom, nevt, me, wgt, evtw, s);
+}
+
 }  // namespace mg

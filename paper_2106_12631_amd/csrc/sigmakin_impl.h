@@ -169,19 +169,19 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// Matrix-core colour sum of one helicity per lane, kept out of line: with
-// the MFMA code inlined after the amplitudes the compiler spills about 1 KB
-// per lane of the amplitude code; behind a call the kernel keeps the
-// register allocation of the FP32 amplitude body and two waves per SIMD
-// (with MFMA results in VGPRs and the callee's saved registers on the stack
-// rather than in AGPRs: the flags of this kernel's source file).  The
-// amplitudes cross the call in LDS, jl[(2 k + part) * 64 + lane]: each lane
-// reads back only its own values, so no barrier is needed.
+// Matrix-core colour sum of one helicity per lane.  The amplitudes reach it
+// through LDS, jl[(2 k + part) * 64 + lane] (each lane reads back only its
+// own values, so no barrier is needed): with the MFMA results in VGPRs
+// (-amdgpu-mfma-vgpr-form, a flag of the mixed sources) the kernel keeps the
+// register allocation of the FP32 amplitude body, 249 VGPRs, no AGPRs and
+// no scratch: two waves per SIMD.  (Out of line behind a call it needed a
+// 72-byte stack frame per lane and ran 1.8 % slower; with the amplitudes
+// passed in registers instead of LDS, 0.4 % slower.)
 typedef __attribute__((address_space(3))) float lds_float;
 
 template <template <int> class CS, int NCOL>
-__device__ __noinline__ float colour_sum_mfma_call(const lds_float* jl, const int* cnum,
-                                                   int lane) {
+__device__ __forceinline__ float colour_sum_mfma_lds(const lds_float* jl, const int* cnum,
+                                                     int lane) {
   CS<NCOL> cs;
   cs.init(cnum, lane);
   return cs.sum_parts([&](int part, int k) { return jl[(2 * k + part) * 64 + lane]; },
@@ -203,13 +203,13 @@ __global__ void __launch_bounds__(64)
   load_event<P>(mom, i, q);
   cx<float> J[P::NCOL];
   P::template jamps<float, true>(q, (unsigned)lane, c, J);
-  __shared__ float jl[2 * P::NCOL * 64];
+__shared__ float jl[2 * P::NCOL * 64];
 #pragma unroll
   for (int k = 0; k < P::NCOL; ++k) {
     jl[(2 * k) * 64 + lane] = J[k].r;
     jl[(2 * k + 1) * 64 + lane] = J[k].i;
   }
-  double v = (double)colour_sum_mfma_call<CS, P::NCOL>((const lds_float*)jl, P::cnum(), lane);
+  double v = (double)colour_sum_mfma_lds<CS, P::NCOL>((const lds_float*)jl, P::cnum(), lane);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   if (lane == 0) {
@@ -217,6 +217,77 @@ __global__ void __launch_bounds__(64)
     if (me) me[i] = m;
     if (evtw) evtw[i] = m * wgt[i];
   }
+}
+
+// Precision guard of the reduced-precision forms.  |M|^2 is ill-conditioned
+// in its invariants when kappa = s / min_{i<j} |2 p_i.p_j| is large (a soft
+// or collinear gluon): single Feynman-gauge diagrams ~ 1/s_ij cancel to an
+// amplitude ~ 1/sqrt(s_ij), so FP32 rounding of the diagram sums grows like
+// eps32 sqrt(kappa).  The guard recomputes in FP64 the events with
+// kappa > kmax after a reduced-precision launch.  One wave scans 64 events
+// (one per lane) and evaluates each flagged event with one helicity per lane
+// (wave-uniform momenta, helicity sum by wave reduction), overwriting me and
+// evtw; the scan finds none in most waves.
+template <int NPAR>
+__device__ __forceinline__ bool ill_conditioned(const double (&p)[NPAR][4], double kmax) {
+  double m = INFINITY;
+#pragma unroll
+  for (int i = 0; i < NPAR; ++i)
+#pragma unroll
+    for (int j = i + 1; j < NPAR; ++j) {
+      const double d = 2.0 * (p[i][0] * p[j][0] - p[i][1] * p[j][1] - p[i][2] * p[j][2] -
+                              p[i][3] * p[j][3]);
+      m = fmin(m, fabs(d));
+    }
+  const double E = p[0][0] + p[1][0], X = p[0][1] + p[1][1], Y = p[0][2] + p[1][2],
+               Z = p[0][3] + p[1][3];
+  return E * E - X * X - Y * Y - Z * Z > kmax * m;
+}
+
+template <class P>
+__global__ void __launch_bounds__(64)
+    sigmakin_guard_kernel(const double* __restrict__ mom, int64_t nevt, double* __restrict__ me,
+                          const double* __restrict__ wgt, double* __restrict__ evtw, HelList hl,
+                          Couplings<double> c, double inv_iden, double kmax) {
+  const int lane = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  bool flag = false;
+  if (i0 + lane < nevt) {
+    double q[P::NPAR][4];
+    load_event<P>(mom, i0 + lane, q);
+    flag = ill_conditioned<P::NPAR>(q, kmax);
+  }
+  uint64_t pending = __ballot(flag);
+  while (pending) {
+    const int l = __ffsll((unsigned long long)pending) - 1;
+    pending &= pending - 1;
+    const int64_t e = i0 + l;
+    double q[P::NPAR][4];
+    load_event<P>(mom, e, q);
+    double v = 0.0;
+    for (int k = lane; k < hl.n; k += 64) {
+      cx<double> J[P::NCOL];
+      P::template jamps<double, true>(q, hl.code[k], c, J);
+      v += P::template colour_sum<double>(J);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) {
+      const double m = v * inv_iden;
+      me[e] = m;
+      if (evtw) evtw[e] = m * wgt[e];
+    }
+  }
+}
+
+template <class P>
+int sigmakin_guard_launch(const MeArgs& a, const double* mom, int64_t nevt, double* me,
+                          const double* wgt, double* evtw, hipStream_t s) {
+  if (!(a.guard_kappa > 0.0) || nevt <= 0) return 0;
+  const unsigned g = (unsigned)((nevt + 63) / 64);
+  sigmakin_guard_kernel<P><<<g, 64, 0, s>>>(mom, nevt, me, wgt, evtw, a.hel, a.c64, a.inv_iden,
+                                            a.guard_kappa);
+  return 0;
 }
 
 // helicity-per-lane mixed launch when every helicity is kept, else the

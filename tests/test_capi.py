@@ -53,3 +53,15 @@ def test_generator_diagram_counts_and_colour_matrix():
         pd = ProcessDiagrams(p)
         coefs = pd.jamp_coefficients()
         assert len(coefs) == len(pd.diagrams) and all(coefs)
+
+
+def test_binding_constants_match_the_header():
+    """The binding's flag bits and the Params struct follow include/mg5mi.h."""
+    import paper_2106_12631_amd as mg
+    src = open(HEADER).read()
+    flags = dict((n, int(v)) for n, v in re.findall(r'#define MG_(FLAG_\w+) (\d+)', src))
+    assert flags and all(getattr(mg, n) == v for n, v in flags.items())
+    body = re.search(r'typedef struct \{(.*?)\} mg_params_t;', src, re.S).group(1)
+    fields = re.findall(r'^\s*(double|int)\s+([\w, ]+);', body, re.M)
+    names = [x.strip() for _, decl in fields for x in decl.split(',')]
+    assert [f[0] for f in mg.Params._fields_] == names
