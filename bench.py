@@ -64,8 +64,10 @@ def kernel_source_hash(proc):
     from paper_2106_12631_amd import build as _build
     csrc = os.path.join(ROOT, 'paper_2106_12631_amd', 'csrc')
     shared = ['colour_mfma.h', 'common.h', 'helas.h', 'internal.h', 'sigmakin_impl.h']
-    names = shared + sorted(n for n in os.listdir(csrc)
-                            if n.startswith(f'sigmakin_{proc}_') and n.endswith('.hip'))
+    gen = os.path.join(csrc, 'generated')
+    units = sorted(os.path.join('generated', n) for n in os.listdir(gen)
+                   if n.startswith(f'sigmakin_{proc}_') and n.endswith('.hip'))
+    names = shared + units
     h = hashlib.sha256()
     for n in names + [os.path.join('generated', f'{proc}.inc')]:
         h.update(n.encode())
@@ -73,7 +75,7 @@ def kernel_source_hash(proc):
             h.update(fh.read())
     h.update(' '.join(a for a in _build.FLAGS if not a.startswith('/')).encode())
     for n in names:
-        h.update(' '.join(_build.SOURCE_FLAGS.get(n, ())).encode())
+        h.update(' '.join(_build.SOURCE_FLAGS.get(os.path.basename(n), ())).encode())
     return h.hexdigest()[:16]
 
 

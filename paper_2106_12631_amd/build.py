@@ -1,7 +1,8 @@
 """Build the gfx950 shared library libmg5mi.so in-tree.
 
-Steps: run the diagram generator (gen/) to emit csrc/generated/*.inc, compile
-every csrc/*.hip with hipcc for gfx950, link one shared library next to this
+Steps: run the diagram generator (gen/) to emit csrc/generated/ (the
+amplitude code *.inc and the per-process kernel units *.hip), compile every
+csrc/*.hip and csrc/generated/*.hip with hipcc for gfx950, link one shared library next to this
 file; then build the calibration kernels (calib/) as libmg5cal.so.
 
     python -m paper_2106_12631_amd.build               build both libraries
@@ -39,7 +40,13 @@ SOURCE_FLAGS = {
 
 
 def sources():
-    return sorted(f for f in os.listdir(CSRC) if f.endswith('.hip'))
+    """Hand-written units of csrc/ and the per-process units the generator
+    writes to csrc/generated/ (file names are unique across the two)."""
+    gen = os.path.join(CSRC, 'generated')
+    units = [f for f in os.listdir(CSRC) if f.endswith('.hip')]
+    if os.path.isdir(gen):
+        units += [os.path.join('generated', f) for f in os.listdir(gen) if f.endswith('.hip')]
+    return sorted(units)
 
 
 def build(force=True, verbose=True, extra_flags=(), output=None):
@@ -51,9 +58,9 @@ def build(force=True, verbose=True, extra_flags=(), output=None):
     objs = []
     t0 = time.time()
     for src in sources():
-        obj = os.path.join(BUILD, src.replace('.hip', '.o'))
+        obj = os.path.join(BUILD, os.path.basename(src).replace('.hip', '.o'))
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, ()), *extra_flags, '-c',
+        cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(os.path.basename(src), ()), *extra_flags, '-c',
                os.path.join(CSRC, src), '-o', obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
@@ -93,8 +100,9 @@ def resource_report():
     import re
     rows = []
     for src in sources():
-        cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, ()), '-Rpass-analysis=kernel-resource-usage',
-               '-c', os.path.join(CSRC, src), '-o', os.devnull]
+        cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(os.path.basename(src), ()),
+               '-Rpass-analysis=kernel-resource-usage', '-c', os.path.join(CSRC, src), '-o',
+               os.devnull]
         out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
                              text=True).stdout
         cur = None
@@ -105,7 +113,7 @@ def resource_report():
                 continue
             key, val = m.group(1).split(' [')[0], m.group(2)
             if key == 'Function Name':
-                cur = {'source': src, 'kernel': val}
+                cur = {'source': os.path.basename(src), 'kernel': val}
                 rows.append(cur)
             elif cur is not None:
                 cur[key] = val

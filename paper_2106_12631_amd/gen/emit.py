@@ -16,7 +16,8 @@ fused multiply-add = 2, divide, square root = 1).
 import json
 import os
 
-from .diagrams import BOSON_MASS, FERMION_MASS, FFV, ProcessDiagrams, colour_matrix, IN, OUT
+from .diagrams import (BOSON_MASS, FERMION_MASS, FFV, IN, OUT, PROCESSES, ProcessDiagrams,
+                       colour_matrix)
 
 IDEN = {'eemumu': 4, 'ggtt': 256, 'ggttg': 256, 'ggttgg': 512}
 
@@ -898,6 +899,123 @@ def generate(name, orders=None):
     return "\n".join(L) + "\n", meta
 
 
+# One event per wave and one helicity per lane: the processes whose 64
+# helicities fill a wave64 (all kept at the benchmark parameters).
+HPL_PROCESSES = ('ggttgg',)
+
+
+def emit_units(name):
+    """{file name: source} of the translation units that instantiate the
+    kernels of sigmakin_impl.h and adjoint_impl.h for one process: the
+    process traits (amplitude bodies and colour sum of the generated code)
+    and the launchers the C ABI calls, per precision."""
+    hpl = name in HPL_PROCESSES
+    head = (f'// Generated for {name}: do not edit.  Kernels of sigmakin_impl.h for this\n'
+            f'// process, {{what}}.\n')
+    traits = f'''struct P_{name} {{
+  static constexpr int NPAR = gen_{name}::NPAR;
+  static constexpr int NCOL = gen_{name}::NCOL;
+  static constexpr int CDEN = gen_{name}::CDEN;
+  __device__ static __forceinline__ const int* cnum() {{ return &gen_{name}::CNUM[0][0]; }}
+  template <typename T, bool UNI = false>
+  __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
+                                               const Couplings<T>& c, cx<T> (&J)[NCOL]) {{
+    gen_{name}::{{body}}(p, h, c, J);
+  }}
+  template <typename T>
+  __device__ static __forceinline__ T colour_sum(const cx<T> (&J)[NCOL]) {{
+    return gen_{name}::colour_sum<T>(J);
+  }}
+}};
+'''
+    sk_args = '(const MeArgs& a, const double* mom, int64_t nevt, double* me, const double* wgt,\n' \
+              '    double* evtw, double* mehel, hipStream_t s)'
+    units = {}
+    for prec, T, c in (('f64', 'double', 'c64'), ('f32', 'float', 'c32')):
+        epl = f'sigmakin_launch<P_{name}, {T}, MG_EPL_BLOCK>(a, a.{c}, mom, nevt, me, wgt, evtw, mehel, s)'
+        if hpl:
+            body = (f'#ifdef MG_EVENT_PER_LANE_{prec.upper()}\n'
+                    f'  return sigmakin_launch<P_{name}, {T}, 64>(a, a.{c}, mom, nevt, me, wgt, evtw, mehel, s);\n'
+                    f'#else\n'
+                    f'  return sigmakin_hpl_launch<P_{name}, {T}, 64>(a, a.{c}, mom, nevt, me, wgt, evtw, mehel, s);\n'
+                    f'#endif\n')
+        else:
+            body = f'  return {epl};\n'
+        src = head.format(what=f'{T} amplitudes') + '#include "sigmakin_impl.h"\n\nnamespace mg {\n' \
+            f'#include "{name}.inc"\n\n' + traits.replace('{body}', 'jamps<T, UNI>') + '\n' \
+            f'int launch_sigmakin_{name}_{prec}{sk_args} {{\n{body}}}\n'
+        if prec == 'f64':
+            src += (f'\n// FP64 recomputation of the ill-conditioned events of a reduced-precision\n'
+                    f'// launch (precision guard of sigmakin_impl.h)\n'
+                    f'int launch_sigmakin_{name}_guard(const MeArgs& a, const double* mom, int64_t nevt,\n'
+                    f'    double* me, const double* wgt, double* evtw, hipStream_t s) {{\n'
+                    f'  return sigmakin_guard_launch<P_{name}>(a, mom, nevt, me, wgt, evtw, s);\n}}\n')
+        units[f'sigmakin_{name}_{prec}.hip'] = src + '\n}  // namespace mg\n'
+    # mixed: event-per-lane body for the matrix-core colour sum (jamps_f32m)
+    # and, for the helicity-per-lane processes, the FP32 body of that kernel
+    mt = traits.replace('{body}', 'jamps_f32m').replace('template <typename T, bool UNI = false>\n'
+                                                        '  __device__ static __forceinline__ void jamps(',
+                                                        'template <typename T, bool UNI = false>\n'
+                                                        '  __device__ static __forceinline__ void jamps(')
+    mt = mt.replace('const Couplings<T>& c, cx<T> (&J)[NCOL]', 'const Couplings<float>& c, cx<float> (&J)[NCOL]')
+    src = head.format(what='FP32 amplitudes and the matrix-core colour sum') + \
+        '#include "sigmakin_impl.h"\n\nnamespace mg {\n' + f'#include "{name}.inc"\n\n' + mt
+    if hpl:
+        src += f'''
+struct P_{name}_hpl : P_{name} {{
+  template <typename T, bool UNI = false>
+  __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
+                                               const Couplings<float>& c, cx<float> (&J)[NCOL]) {{
+    gen_{name}::jamps<float, UNI>(p, h, c, J);
+  }}
+}};
+'''
+    for cs, tag in (('ColourMfmaF32', 'f32'), ('ColourMfmaBf16', 'bf16')):
+        call = (f'sigmakin_mixed_hpl_launch<P_{name}, P_{name}_hpl, {cs}>' if hpl
+                else f'sigmakin_mixed_launch<P_{name}, {cs}>')
+        src += (f'\nint launch_sigmakin_{name}_mfma_{tag}(const MeArgs& a, const double* mom, int64_t nevt,\n'
+                f'    double* me, const double* wgt, double* evtw, hipStream_t s) {{\n'
+                f'  return {call}(a, mom, nevt, me, wgt, evtw, s);\n}}\n')
+    units[f'sigmakin_{name}_mixed.hip'] = src + '\n}  // namespace mg\n'
+    if name in GRAD_PROCESSES:
+        nf = len(PROCESSES[name]) - 2
+        src = (f'// Generated for {name}: do not edit.  Gradient kernels of adjoint_impl.h for\n'
+               f'// this process (adjoint_a64: FP64, adjoint_a32: FP32 amplitudes).\n'
+               '#include "adjoint_impl.h"\n\nnamespace mg {\n' + f'#include "{name}.inc"\n')
+        for prec, T in (('a64', 'double'), ('a32', 'float')):
+            src += f'''
+struct {prec.upper()}_{name} {{
+  __device__ static __forceinline__ double adjoint(double (&p)[gen_{name}::NPAR][4], unsigned h,
+                                                   const Couplings<{T}>& c,
+                                                   double (&pb)[gen_{name}::NPAR][4]) {{
+    return gen_{name}::adjoint_{prec}(p, h, c, pb);
+  }}
+}};
+'''
+        src += f'''
+int launch_grad_{name}(int prec, const MeArgs& a, const RamboArgs& ra, const double* rnd,
+    int64_t nevt, const double* gbar, double* grad_rnd, double* grad_logw, double* mew,
+    hipStream_t s) {{
+  if (prec == 0)
+    return adjoint_launch<A64_{name}, {nf}, double>(a, ra, a.c64, rnd, nevt, gbar, grad_rnd,
+                                                   grad_logw, mew, s);
+  return adjoint_launch<A32_{name}, {nf}, float>(a, ra, a.c32, rnd, nevt, gbar, grad_rnd,
+                                                grad_logw, mew, s);
+}}
+
+}}  // namespace mg
+'''
+        units[f'grad_{name}.hip'] = src
+    return units
+
+
+def _write_if_changed(path, src):
+    old = open(path).read() if os.path.exists(path) else None
+    if old != src:
+        with open(path, 'w') as f:
+            f.write(src)
+
+
 def write_all(outdir):
     os.makedirs(outdir, exist_ok=True)
     metas = {}
@@ -905,11 +1023,9 @@ def write_all(outdir):
     orders = optimised_orders(names)
     for name in names:
         src, meta = generate(name, orders)
-        path = os.path.join(outdir, f"{name}.inc")
-        old = open(path).read() if os.path.exists(path) else None
-        if old != src:
-            with open(path, 'w') as f:
-                f.write(src)
+        _write_if_changed(os.path.join(outdir, f"{name}.inc"), src)
+        for fname, usrc in emit_units(name).items():
+            _write_if_changed(os.path.join(outdir, fname), usrc)
         metas[name] = meta
     with open(os.path.join(outdir, 'meta.json'), 'w') as f:
         json.dump(metas, f, indent=1, sort_keys=True)
