@@ -20,6 +20,36 @@
 
 namespace mg {
 
+// Adjoint accumulators of the reverse sweep in LDS (when the generated code
+// has slots): slot s of a lane is 4 complex values at base + s * SLOT, with
+// the lanes of a slot LANE bytes apart (8 bytes of padding per lane spread
+// the accesses of consecutive lanes over the banks; 16 bytes run as fast but
+// take 11 % more LDS).  Every access launders the address, so the compiler
+// keeps no accumulator in registers across the sweep: the registers stay
+// with the recomputed forward values.  The slots of a 64-lane block must
+// leave room for four blocks per CU (40 KB each).
+typedef __attribute__((address_space(3))) char lds_char;
+
+#ifndef MG_ADJ_LANE_PAD
+#define MG_ADJ_LANE_PAD 8
+#endif
+template <typename T>
+struct AdjSlots {
+  static constexpr int LANE = 4 * (int)sizeof(cx<T>) + MG_ADJ_LANE_PAD;
+  static constexpr int SLOT = 64 * LANE;
+  lds_char* base;  // this lane's slot 0
+  __device__ __forceinline__ cx<T>* slot(int s) const {
+    int off = s * SLOT;
+    asm volatile("" : "+v"(off));
+    return (cx<T>*)(base + off);
+  }
+  __device__ __forceinline__ void clear(int s) const {
+    cx<T>* w = slot(s);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = cx<T>{(T)0, (T)0};
+  }
+};
+
 template <class P, int NF, typename T>
 __global__ void __launch_bounds__(64)
     adjoint_kernel(const double* __restrict__ rnd, int64_t nevt, RamboArgs ra, HelList hl,
@@ -41,8 +71,11 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
     for (int m = 0; m < 4; ++m) pb[l][m] = 0.0;
   double me = 0.0;
+  static_assert(P::SLOTS * AdjSlots<T>::SLOT <= 40 * 1024, "adjoint slots: four blocks per CU");
+  __shared__ char slots[P::SLOTS > 0 ? P::SLOTS * AdjSlots<T>::SLOT : 1];
+  const AdjSlots<T> ws{(lds_char*)(slots + threadIdx.x * AdjSlots<T>::LANE)};
 #pragma nounroll
-  for (int h = 0; h < hl.n; ++h) me += P::adjoint(p, hl.code[h], c, pb);
+  for (int h = 0; h < hl.n; ++h) me += P::adjoint(p, hl.code[h], c, pb, ws);
   const double g = gbar ? gbar[i] : 1.0;
   // the uniforms are read again rather than kept live across the helicity
   // loop (an opaque index keeps the compiler from reusing the first loads)

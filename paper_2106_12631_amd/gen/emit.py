@@ -487,7 +487,7 @@ def _legs_of(n):
     return n.legs
 
 
-def emit_adjoint_body(pd, coefs, order, bils, need, budget):
+def emit_adjoint_body(pd, coefs, order, bils, need, budget, lds=False, lds_span=0, spans=None):
     """Reverse sweep of jamps() for one helicity: the colour-flow adjoints
     Jb (already formed) are propagated back through the amplitude terms (in
     reverse order) and the wavefunctions (each once all its consumers are
@@ -495,8 +495,12 @@ def emit_adjoint_body(pd, coefs, order, bils, need, budget):
     final-state legs.  Forward values are recomputed from the externals
     under the same live-wavefunction budget as the forward code (Belady
     eviction).  Wavefunctions whose legs are all initial-state carry no
-    momentum dependence and are not differentiated.  Returns (lines,
-    executed flops)."""
+    momentum dependence and are not differentiated.  With lds the adjoint
+    accumulators live in slots of the workgroup's LDS (ws.slot(s), reused
+    once a wavefunction has been back-propagated) instead of registers,
+    except those open for at most lds_span steps (spans: {node: steps} of a
+    previous pass; short-lived ones stay in registers).  Returns (lines,
+    executed flops, number of slots, {node: steps open})."""
     import bisect
     parts = pd.particles
     npar = pd.npar
@@ -579,16 +583,39 @@ def emit_adjoint_body(pd, coefs, order, bils, need, budget):
         return name
 
     declared = set()
+    slot_of, free_slots, nslots = {}, [], [0]
+    opened, span_of = {}, {}
+    cur_step = [0]
+
+    def in_lds(n):
+        return lds and (spans is None or spans.get(n.idx, 10 ** 9) > lds_span)
 
     def bar(n):
         """Name of n's adjoint accumulator (declared on first use), or a sink."""
         if not final(n):
             return None
+        opened.setdefault(n.idx, cur_step[0])
+        if in_lds(n):
+            if n.idx not in slot_of:
+                if free_slots:
+                    slot_of[n.idx] = free_slots.pop()
+                else:
+                    slot_of[n.idx] = nslots[0]
+                    nslots[0] += 1
+                L.append(f"  ws.clear({slot_of[n.idx]});")
+            return f"ws.slot({slot_of[n.idx]})"
         nm = f"wb{n.idx - 10 ** 6}b" if isinstance(n, Bil) else f"wb{n.idx}"
         if n.idx not in declared:
             declared.add(n.idx)
             L.append(f"  cx<T> {nm}[4] = {{{{(T)0, (T)0}}, {{(T)0, (T)0}}, {{(T)0, (T)0}}, {{(T)0, (T)0}}}};")
         return nm
+
+    def release(n):
+        """n has been back-propagated: its slot takes the next accumulator."""
+        if n.idx in opened:
+            span_of[n.idx] = cur_step[0] - opened[n.idx]
+        if n.idx in slot_of:
+            free_slots.append(slot_of.pop(n.idx))
 
     sink_count = [0]
 
@@ -606,6 +633,7 @@ def emit_adjoint_body(pd, coefs, order, bils, need, budget):
                 L.append(f"  for (int m = 0; m < 4; ++m) pb[{l}][m] -= (double){kname}[m];")
 
     for si, st in enumerate(steps):
+        cur_step[0] = si
         if si % ADJ_FENCE_EVERY == 0:
             L.append("  fence(p);")
         if st[0] == 'amp':
@@ -640,6 +668,7 @@ def emit_adjoint_body(pd, coefs, order, bils, need, budget):
                 L.append(f"  adj_bilinear<T>({dn[0]}, {dn[1]}, c.{cl}, c.{cr}, {wb}, "
                          f"{acc(deps[0])}, {acc(deps[1])});")
                 execd += ADJ_FLOPS['bilinear']
+                release(n)
                 continue
             if op[0] == 'ext':
                 l, routine = op[1], op[2]
@@ -655,6 +684,7 @@ def emit_adjoint_body(pd, coefs, order, bils, need, budget):
                           'v': ('adj_ext_v', 'false'), 'vbar': ('adj_ext_v', 'true')}[routine]
                     L.append(f"  {fn[0]}<T>(p[{l}], {mass}, {hel}, {fn[1]}, {wb}, pb[{l}]);")
                 execd += ADJ_FLOPS['ext']
+                release(n)
                 continue
             K = _ksum(n.legs, parts)
             accs = {x.idx: acc(x) for x in deps}
@@ -709,7 +739,8 @@ def emit_adjoint_body(pd, coefs, order, bils, need, budget):
                     if parts[l][1] == OUT:
                         L.append(f"    for (int m = 0; m < 4; ++m) pb[{l}][m] -= (double)Kb[m];")
             L.append("  }")
-    return L, execd
+            release(n)
+    return L, execd, nslots[0], span_of
 
 
 # register budget in live wavefunctions (4 complex each) per precision, the
@@ -739,6 +770,25 @@ FENCE = {'f64': 4, 'f32': 8, 'f32m': 12, 'a64': 4, 'a32': 4}
 
 # reverse-sweep steps between two fences in the adjoint code
 ADJ_FENCE_EVERY = int(os.environ.get('MG_ADJ_FENCE_EVERY', 4))
+
+
+# (process, precision) pairs whose adjoint accumulators live in LDS slots
+# (MG_ADJ_LDS=ggttg:a64,...; 'none' for none).  FP64 g g -> t t~ g: in
+# registers its reverse sweep needs 512 registers and 1.8 KB of scratch per
+# lane (10.1 ms for 2^18 events); with the accumulators open for more than 6
+# reverse steps in 8 LDS slots (36.9 KB per wave, four waves per CU) 6.1 ms.
+# Its FP32 sweep fits registers better and runs slower from LDS (5.3 against
+# 4.3 ms), as do the smaller processes, which do not spill.
+ADJ_LDS = tuple(tuple(x.split(':')) for x in
+                os.environ.get('MG_ADJ_LDS', 'ggttg:a64').split(',') if ':' in x)
+# accumulators open for at most this many reverse steps stay in registers
+# (g g -> t t~ g: 6 -> 8 slots, 6.1 ms; 8 -> 7 slots, 6.2 ms; 12 -> 6 slots,
+# 6.7 ms; 0 -> 9 slots, 46 KB, three waves per CU, 9.4 ms)
+ADJ_LDS_SPAN = int(os.environ.get('MG_ADJ_LDS_SPAN', 6))
+
+
+def _adj_lds(name, prec):
+    return (name, prec) in ADJ_LDS
 
 
 def _fence(prec):
@@ -857,13 +907,21 @@ def generate(name, orders=None):
             order = orders[(name, budget)]
             fwd, algo, execd, peak, rec = emit_body(pd, coefs, order, bils, need, budget,
                                                     fence_every=_fence(prec))
-            rev, rexec = emit_adjoint_body(pd, coefs, order, bils, need, budget)
-            stats[prec] = dict(flops_forward_executed_per_hel=execd, flops_reverse_executed_per_hel=rexec)
+            _, _, _, spans = emit_adjoint_body(pd, coefs, order, bils, need, budget)
+            rev, rexec, nslots, _ = emit_adjoint_body(pd, coefs, order, bils, need, budget,
+                                                      lds=_adj_lds(name, prec), lds_span=ADJ_LDS_SPAN,
+                                                      spans=spans)
+            stats[prec] = dict(flops_forward_executed_per_hel=execd, flops_reverse_executed_per_hel=rexec,
+                               adjoint_lds_slots=nslots)
+            A.append(f"// LDS slots of the adjoint accumulators (0: kept in registers)")
+            A.append(f"constexpr int ADJ_SLOTS_{prec} = {nslots};")
             A.append(f"// reverse mode: returns the colour-summed |M|^2 of helicity hcode and adds")
-            A.append(f"// its gradient with respect to the momenta of the final-state legs to pb")
+            A.append(f"// its gradient with respect to the momenta of the final-state legs to pb;")
+            A.append(f"// ws: the lane's adjoint slots (ws.slot(s), ws.clear(s)) when ADJ_SLOTS > 0")
+            A.append(f"template <class WS>")
             A.append(f"__device__ __forceinline__ double adjoint_{prec}(double (&p)[{npar}][4], unsigned hcode,")
             A.append(f"                                            const Couplings<{Ct}>& c,")
-            A.append(f"                                            double (&pb)[{npar}][4]) {{")
+            A.append(f"                                            double (&pb)[{npar}][4], const WS& ws) {{")
             A.append(f"  using T = {T};")
             A.append(f"  using R = double;")
             A.append(f"  constexpr bool UNI = false;")
@@ -985,10 +1043,12 @@ struct P_{name}_hpl : P_{name} {{
         for prec, T in (('a64', 'double'), ('a32', 'float')):
             src += f'''
 struct {prec.upper()}_{name} {{
+  static constexpr int SLOTS = gen_{name}::ADJ_SLOTS_{prec};
+  template <class WS>
   __device__ static __forceinline__ double adjoint(double (&p)[gen_{name}::NPAR][4], unsigned h,
                                                    const Couplings<{T}>& c,
-                                                   double (&pb)[gen_{name}::NPAR][4]) {{
-    return gen_{name}::adjoint_{prec}(p, h, c, pb);
+                                                   double (&pb)[gen_{name}::NPAR][4], const WS& ws) {{
+    return gen_{name}::adjoint_{prec}(p, h, c, pb, ws);
   }}
 }};
 '''
