@@ -430,6 +430,14 @@ def main():
                              "frac": achieved / peak, "traffic": traffic.get(prec),
                              "flops_per_event": flops_evt},
             }
+            if calibration:
+                # against what a stream of independent FMAs of the same
+                # precision reaches on this chip (unpacked FP32: packed FP32
+                # instructions are disabled in every build)
+                cal = calibration['fp64_vector_fma' if prec == 'fp64'
+                                  else 'fp32_vector_fma_unpacked']['achieved_TFLOPs']
+                v["roofline"]["calibrated_peak"] = cal
+                v["roofline"]["frac_vs_calibrated"] = achieved / 1e12 / cal
             if prec.startswith('mixed'):
                 v["mfma"] = mfma_work(meta['ncol'], nhel, prec, proc, k_avg, nevt)
             if name in cpu:
