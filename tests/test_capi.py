@@ -65,3 +65,10 @@ def test_binding_constants_match_the_header():
     fields = re.findall(r'^\s*(double|int)\s+([\w, ]+);', body, re.M)
     names = [x.strip() for _, decl in fields for x in decl.split(',')]
     assert [f[0] for f in mg.Params._fields_] == names
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(ROOT, 'paper_2106_12631_amd', 'libmg5cal.so')),
+                    reason="calibration library not built")
+def test_calibration_library_exports_its_entry_point():
+    L = ctypes.CDLL(os.path.join(ROOT, 'paper_2106_12631_amd', 'libmg5cal.so'))
+    assert hasattr(L, 'mgcal_run')

@@ -58,3 +58,18 @@ def test_plateau_workload_parity():
     assert float(((me_gpu - own).abs() / own).max()) <= 1e-12
     want = orc.matrix_element('eemumu', p)
     assert bool((((me_gpu - want).abs() / want) <= end_to_end_bound(r, p)).all())
+
+
+def test_calibration_kernels():
+    """The calibration streams run and reach a plausible share of the
+    published peaks (between 30 % and 105 %), so the bench's calibrated
+    roofline fractions rest on working kernels."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_12631_amd import calibrate
+    print('[gpu-test] calibration kernels', flush=True)
+    res = calibrate.run(blocks=512)
+    assert set(res) == {k[0] for k in calibrate.KINDS.values()}
+    for name, r in res.items():
+        print('[gpu-test]', name, round(r['achieved_TFLOPs'], 1), 'TFLOP/s', flush=True)
+        assert 0.3 <= r['frac'] <= 1.05, name
