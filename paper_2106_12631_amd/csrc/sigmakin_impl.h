@@ -22,6 +22,18 @@
 #define MG_EPL_BLOCK 256
 #endif
 
+// Launches of fewer events than a per-process threshold (written by the
+// generator) use several lanes per event (one kept helicity per lane,
+// sigmakin_group_kernel) in the event-per-lane processes;
+// -DMG_GROUP_MAX_EVENTS=n sets one threshold for all of them.
+constexpr int64_t group_max_events(int64_t per_process) {
+#ifdef MG_GROUP_MAX_EVENTS
+  return (int64_t)(MG_GROUP_MAX_EVENTS) + 0 * per_process;
+#else
+  return per_process;
+#endif
+}
+
 namespace mg {
 
 // Workgroups are handed to the 8 XCDs of the chip in turn (block b to XCD
@@ -167,6 +179,57 @@ __global__ void __launch_bounds__(64)
     if (me) me[i] = m;
     if (evtw) evtw[i] = m * wgt[i];
   }
+}
+
+// Several lanes per event, one kept helicity per lane: for L = hl.n kept
+// helicities (a power of two up to 64), 64 / L events per wave, lane k of an
+// event's group computing helicity hl.code[k]; the helicity sum is a
+// butterfly over the group.  Every lane loads its event's momenta (the
+// group's lanes read the same lines).  For small launches it spreads the
+// helicity loop of the event-per-lane kernel over L times more lanes.  The
+// groups of events past nevt return whole, so every butterfly stays inside
+// active lanes.
+template <class P, typename T, int BS>
+__global__ void __launch_bounds__(BS)
+    sigmakin_group_kernel(const double* __restrict__ mom, int64_t nevt, double* __restrict__ me,
+                          const double* __restrict__ wgt, double* __restrict__ evtw, HelList hl,
+                          Couplings<T> c, double inv_iden, int lanes_log2) {
+  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int64_t i = t >> lanes_log2;
+  const int L = 1 << lanes_log2;
+  const int k = (int)(t & (L - 1));
+  if (i >= nevt) return;
+  double q[P::NPAR][4];
+  load_event<P>(mom, i, q);
+  cx<T> J[P::NCOL];
+  P::template jamps<T>(q, hl.code[k], c, J);
+  double v = (double)P::template colour_sum<T>(J);
+  for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (k == 0) {
+    const double m = v * inv_iden;
+    if (me) me[i] = m;
+    if (evtw) evtw[i] = m * wgt[i];
+  }
+}
+
+// the group kernel when the kept helicities are a power of two and the
+// launch has fewer than `max_events` events (where the event-per-lane kernel
+// leaves compute units idle), else the event-per-lane kernel
+template <class P, typename T, int BS>
+int sigmakin_group_launch(const MeArgs& a, const Couplings<T>& c, const double* mom, int64_t nevt,
+                          double* me, const double* wgt, double* evtw, double* mehel,
+                          int64_t max_events, hipStream_t s) {
+  const int n = a.hel.n;
+  if (!mehel && nevt > 0 && nevt < max_events && n > 1 && n <= 64 && (n & (n - 1)) == 0) {
+    int lg = 0;
+    while ((1 << lg) < n) ++lg;
+    const int64_t threads = nevt << lg;
+    const unsigned g = (unsigned)((threads + BS - 1) / BS);
+    sigmakin_group_kernel<P, T, BS><<<g, BS, 0, s>>>(mom, nevt, me, wgt, evtw, a.hel, c,
+                                                     a.inv_iden, lg);
+    return 0;
+  }
+  return sigmakin_launch<P, T, BS>(a, c, mom, nevt, me, wgt, evtw, mehel, s);
 }
 
 // Matrix-core colour sum of one helicity per lane.  The amplitudes reach it

@@ -960,6 +960,13 @@ def generate(name, orders=None):
 # One event per wave and one helicity per lane: the processes whose 64
 # helicities fill a wave64 (all kept at the benchmark parameters).
 HPL_PROCESSES = ('ggttgg',)
+# Launches of fewer events than this use the group kernel (one kept helicity
+# per lane, several lanes per event) instead of the event-per-lane kernel:
+# the crossovers of the events-per-launch sweep (FP64, SIGMAKIN only; group
+# against event per lane: e+e- -> mu+mu- 1.9x at 4096-16384 events, 1.04x at
+# 2^20, equal at 2^24; g g -> t t~ 5.6x at 4096, 1.01x at 2^17, 0.97x from
+# 2^18; g g -> t t~ g 9.6x at 4096, 1.5x at 2^15, 0.87x from 2^16)
+GROUP_MAX_EVENTS = {'eemumu': 1 << 21, 'ggtt': 1 << 17, 'ggttg': 1 << 16}
 
 
 def emit_units(name):
@@ -990,7 +997,8 @@ def emit_units(name):
               '    double* evtw, double* mehel, hipStream_t s)'
     units = {}
     for prec, T, c in (('f64', 'double', 'c64'), ('f32', 'float', 'c32')):
-        epl = f'sigmakin_launch<P_{name}, {T}, MG_EPL_BLOCK>(a, a.{c}, mom, nevt, me, wgt, evtw, mehel, s)'
+        epl = (f'sigmakin_group_launch<P_{name}, {T}, MG_EPL_BLOCK>(a, a.{c}, mom, nevt, me, wgt, evtw,\n'
+               f'      mehel, group_max_events({GROUP_MAX_EVENTS.get(name, 0)}), s)')
         if hpl:
             body = (f'#ifdef MG_EVENT_PER_LANE_{prec.upper()}\n'
                     f'  return sigmakin_launch<P_{name}, {T}, 64>(a, a.{c}, mom, nevt, me, wgt, evtw, mehel, s);\n'

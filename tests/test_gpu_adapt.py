@@ -140,9 +140,11 @@ def test_adaptation_ggtt_coupling_flow(mg):
     torch.manual_seed(0)
     e = mg.MEEngine('ggtt')
     res = adapt.adapt_process(e, seed=4, iters=200, batch=1 << 14, nbins=16, lr=0.003,
-                              eval_batch=1 << 18, clip=1.0, flow='coupling', mix=0.1, log=say)
+                              eval_batch=1 << 18, clip=0.995, flow='coupling', mix=0.1, log=say)
     _agree(res)
-    # 7.4x for these seeds (deterministic training)
+    # 10.4x to 10.7x over training seeds 4, 6, 8: the loss on weights capped
+    # at the batch's 99.5 % quantile keeps rare large weights from steering
+    # the training (uncapped: 1.2x to 9.6x)
     assert res['variance_reduction'] > 4.0
 
 
@@ -156,5 +158,5 @@ def test_adaptation_ggttg_cut_warp(mg):
     _agree(res)
     h = res['loss_history']
     assert sum(h[-10:]) < sum(h[:10])
-    # 1.58x for these seeds (deterministic training)
+    # capped: 1.53x to 1.58x over training seeds 4, 6, 8
     assert res['capped_variance_reduction'] > 1.2

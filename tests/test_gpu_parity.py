@@ -282,3 +282,25 @@ def test_module_shortcuts(mg):
     ref = orc.matrix_element('ggttgg', p)
     assert float(rel(me[:8].cpu(), ref).max()) <= 1e-12
     assert torch.equal(r, orc.sample('ggttgg', 3, 0, n)[0])
+
+
+@pytest.mark.parametrize('proc,n', [('ggtt', (1 << 17) + 37), ('ggttg', (1 << 16) + 37),
+                                    ('eemumu', (1 << 21) + 37)])
+def test_event_per_lane_above_the_group_threshold(mg, proc, n):
+    """Launches above a process's group threshold take the event-per-lane
+    kernel (below it, several lanes per event): a ragged launch of that size
+    against the oracle on the first and last 64 events and 64 seeded others."""
+    e = engine(mg, proc)
+    seed = CONFIG[proc][0]
+    say('event per lane', proc, n)
+    _, mom, _ = e.sample(seed, n)
+    me = e.sigmakin(mom, n)
+    torch.cuda.synchronize()
+    assert e.count_nonfinite(me) == 0
+    g = torch.Generator().manual_seed(n)
+    idx = sorted(set(list(range(64)) + list(range(n - 64, n)) +
+                     torch.randint(0, n, (64,), generator=g).tolist()))
+    p = e.mom_events(mom, n)[idx].cpu()
+    got = me[torch.tensor(idx, device=me.device)].cpu()
+    want = orc.matrix_element(proc, p)
+    assert float(rel(got, want).max()) <= 1e-12
