@@ -172,3 +172,13 @@ def test_two_handles_with_different_parameters(mg):
     _, mom, _ = b.sample(11, n)
     E = b.mom_events(mom, n)[:, :2, 0].cpu()
     assert bool((E == SECOND['sqrts'] / 2).all())
+
+
+def test_unknown_flag_bits_are_rejected(mg):
+    import ctypes
+    L = mg.lib()
+    out = ctypes.c_void_p()
+    bad = mg.Params(**dict(mg.DEFAULT_PARAMS, flags=8))
+    assert L.mg_create(1, 0, ctypes.byref(bad), ctypes.byref(out)) == -1
+    neg = mg.Params(**dict(mg.DEFAULT_PARAMS, wt=-1.0))
+    assert L.mg_create(1, 0, ctypes.byref(neg), ctypes.byref(out)) == -1
