@@ -75,7 +75,7 @@ def kernel_source_hash(proc):
             h.update(fh.read())
     h.update(' '.join(a for a in _build.FLAGS if not a.startswith('/')).encode())
     for n in names:
-        h.update(' '.join(_build.SOURCE_FLAGS.get(os.path.basename(n), ())).encode())
+        h.update(' '.join(_build.source_flags(n)).encode())
     return h.hexdigest()[:16]
 
 

@@ -65,6 +65,7 @@ __global__ void __launch_bounds__(64)
   for (int k = 0; k < NR; ++k) r[k] = rnd[aosoa_rnd(i, k, NR)];
   double p[NP][4], w;
   rambo<NF>(r, ra, p, w);
+  set_beams(p);  // RAMBO's incoming momenta, on the axis: the beam body
   double pb[NP][4];
 #pragma unroll
   for (int l = 0; l < NP; ++l)
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(64)
   __shared__ char slots[P::SLOTS > 0 ? P::SLOTS * AdjSlots<T>::SLOT : 1];
   const AdjSlots<T> ws{(lds_char*)(slots + threadIdx.x * AdjSlots<T>::LANE)};
 #pragma nounroll
-  for (int h = 0; h < hl.n; ++h) me += P::adjoint(p, hl.code[h], c, pb, ws);
+  for (int h = 0; h < hl.n; ++h) me += P::template adjoint<true>(p, hl.code[h], c, pb, ws);
   const double g = gbar ? gbar[i] : 1.0;
   // the uniforms are read again rather than kept live across the helicity
   // loop (an opaque index keeps the compiler from reusing the first loads)

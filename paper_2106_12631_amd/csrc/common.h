@@ -43,4 +43,33 @@ __host__ __device__ inline int64_t aosoa_rnd(int64_t ievt, int irnd, int nrnd) {
   return ((ievt / NEPPR) * nrnd + irnd) * NEPPR + (ievt % NEPPR);
 }
 
+// Incoming momenta along +z and -z with equal energies, (E,0,0,E) and
+// (E,0,0,-E), as RAMBO writes them in the partonic rest frame.  The SIGMAKIN
+// kernels hold the amplitude body twice: for such events with the zero components
+// written as constants (set_beams; jamps<..., BEAM = true>), so that the
+// products with them fold away, and the general body for any other momenta.
+// The test is exact, so both bodies see the same values.  The gradient
+// kernel runs RAMBO itself and takes the beam body only.
+template <int N>
+__device__ __forceinline__ bool beams_on_axis(const double (&p)[N][4]) {
+  const double E = p[0][0];
+  return p[0][1] == 0.0 && p[0][2] == 0.0 && p[0][3] == E && p[1][0] == E &&
+         p[1][1] == 0.0 && p[1][2] == 0.0 && p[1][3] == -E;
+}
+template <int N>
+__device__ __forceinline__ void set_beams(double (&p)[N][4]) {
+  const double E = p[0][0];
+  p[0][1] = 0.0;
+  p[0][2] = 0.0;
+  p[0][3] = E;
+  p[1][0] = E;
+  p[1][1] = 0.0;
+  p[1][2] = 0.0;
+  p[1][3] = -E;
+}
+template <bool B>
+struct Beam {
+  static constexpr bool value = B;
+};
+
 }  // namespace mg

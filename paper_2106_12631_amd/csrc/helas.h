@@ -217,13 +217,16 @@ __device__ __forceinline__ void opaque4(cx<T> (&w)[4]) {
 // not move instructions across the fence.  The generated code orders its
 // work to bound the number of live wavefunctions; the fence keeps that order.
 // With UNI the momenta are the same in every lane of the wave (one event per
-// wave) and stay in scalar registers.
+// wave) and stay in scalar registers.  With BEAM the two incoming momenta
+// are (E,0,0,E) and (E,0,0,-E) with their zero components written as
+// constants (set_beams in the kernels): they stay visible, so products with
+// those zeros fold away in every group.
 __device__ __forceinline__ void opaque_uniform(double& x) { asm volatile("" : "+s"(x)); }
 
-template <bool UNI = false, int N, typename R>
+template <bool UNI = false, bool BEAM = false, int N, typename R>
 __device__ __forceinline__ void fence(R (&p)[N][4]) {
 #pragma unroll
-  for (int k = 0; k < N; ++k)
+  for (int k = BEAM ? 2 : 0; k < N; ++k)
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       if constexpr (UNI) opaque_uniform(p[k][m]);

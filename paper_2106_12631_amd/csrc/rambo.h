@@ -37,6 +37,14 @@ __device__ __forceinline__ dual<F> with_xi_derivative(double xi, const dual<F>* 
   return dual<F>(xi, -xi * num / den);
 }
 
+// A quiet NaN hidden from the optimiser: the gradient units, which run RAMBO
+// inside their kernel, are built with -ffinite-math-only.
+__device__ __forceinline__ double failed_weight() {
+  uint64_t bits = 0x7FF8000000000000ull;
+  asm volatile("" : "+v"(bits));
+  return __builtin_bit_cast(double, bits);
+}
+
 // p[0], p[1] are the incoming momenta along +z and -z; returns false (and a
 // NaN weight) if the Newton solve did not converge.
 template <int NF, typename R>
@@ -134,7 +142,7 @@ __device__ __forceinline__ bool rambo(const R (&r)[4 * NF], const RamboArgs& a,
 #pragma unroll
   for (int k = 0; k < 2 * NF - 3; ++k) xin = xin * xi;
   w = a.w0 * xin * prod * a.sqrts / den;
-  if (!ok) w = __builtin_nan("");
+  if (!ok) w = failed_weight();
   return ok;
 }
 

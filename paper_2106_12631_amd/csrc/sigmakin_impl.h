@@ -66,24 +66,33 @@ __global__ void __launch_bounds__(BS)
                     double* __restrict__ mehel, HelList hl, Couplings<T> c, double inv_iden) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i >= nevt) return;
-  double acc = 0.0;
+  double q0[P::NPAR][4];
+  load_event<P>(mom, i, q0);
+  auto hel_sum = [&](auto beam) {
+    constexpr bool B = decltype(beam)::value;
+    double acc = 0.0;
 #pragma nounroll
-  for (int k = 0; k < hl.n; ++k) {
-    // The momenta are re-read (cache hits) through an event index the
-    // compiler cannot see through, so that no helicity-independent
-    // subexpression (momentum sums, propagator denominators) is hoisted out
-    // of the loop and kept live across it: recomputing them is cheap,
-    // keeping them in registers is not.
-    int64_t iq = i;
-    asm volatile("" : "+v"(iq));
-    double q[P::NPAR][4];
-    load_event<P>(mom, iq, q);
-    cx<T> J[P::NCOL];
-    P::template jamps<T>(q, hl.code[k], c, J);
-    const double v = (double)P::template colour_sum<T>(J);
-    if (mehel) mehel[(int64_t)hl.code[k] * nevt + i] = v;
-    acc += v;
-  }
+    for (int k = 0; k < hl.n; ++k) {
+      // The momenta are re-read (cache hits) through an event index the
+      // compiler cannot see through, so that no helicity-independent
+      // subexpression (momentum sums, propagator denominators) is hoisted
+      // out of the loop and kept live across it: recomputing them is cheap,
+      // keeping them in registers is not.
+      int64_t iq = i;
+      asm volatile("" : "+v"(iq));
+      double q[P::NPAR][4];
+      load_event<P>(mom, iq, q);
+      if constexpr (B) set_beams(q);
+      cx<T> J[P::NCOL];
+      P::template jamps<T, false, B>(q, hl.code[k], c, J);
+      const double v = (double)P::template colour_sum<T>(J);
+      if (mehel) mehel[(int64_t)hl.code[k] * nevt + i] = v;
+      acc += v;
+    }
+    return acc;
+  };
+  // the beam body when every active lane of the wave has its beams on the axis
+  const double acc = __all(beams_on_axis(q0)) ? hel_sum(Beam<true>{}) : hel_sum(Beam<false>{});
   const double m = acc * inv_iden;
   if (me) me[i] = m;
   if (evtw) evtw[i] = m * wgt[i];
@@ -110,20 +119,28 @@ __global__ void __launch_bounds__(64)
   cs.init(P::cnum(), lane);
   cs.save(tab, lane);
   const double scale = inv_iden / P::CDEN;
-  double acc = 0.0;
+  double q0[P::NPAR][4];
+  load_event<P>(mom, il, q0);
+  auto hel_sum = [&](auto beam) {
+    constexpr bool B = decltype(beam)::value;
+    double acc = 0.0;
 #pragma nounroll
-  for (int k = 0; k < hl.n; ++k) {
-    int64_t iq = il;
-    asm volatile("" : "+v"(iq));
-    double q[P::NPAR][4];
-    load_event<P>(mom, iq, q);
-    cx<float> J[P::NCOL];
-    P::template jamps<float>(q, hl.code[k], c, J);
-    int lt = lane;
-    asm volatile("" : "+v"(lt));
-    cs.restore(tab, lt);
-    acc += (double)cs.sum(J, lane);
-  }
+    for (int k = 0; k < hl.n; ++k) {
+      int64_t iq = il;
+      asm volatile("" : "+v"(iq));
+      double q[P::NPAR][4];
+      load_event<P>(mom, iq, q);
+      if constexpr (B) set_beams(q);
+      cx<float> J[P::NCOL];
+      P::template jamps<float, false, B>(q, hl.code[k], c, J);
+      int lt = lane;
+      asm volatile("" : "+v"(lt));
+      cs.restore(tab, lt);
+      acc += (double)cs.sum(J, lane);
+    }
+    return acc;
+  };
+  const double acc = __all(beams_on_axis(q0)) ? hel_sum(Beam<true>{}) : hel_sum(Beam<false>{});
   if (valid) {
     const double m = acc * scale;
     if (me) me[i] = m;
@@ -169,7 +186,12 @@ __global__ void __launch_bounds__(64)
   double q[P::NPAR][4];
   load_event<P>(mom, i, q);
   cx<T> J[P::NCOL];
-  P::template jamps<T, true>(q, h, c, J);
+  if (beams_on_axis(q)) {  // wave-uniform
+    set_beams(q);
+    P::template jamps<T, true, true>(q, h, c, J);
+  } else {
+    P::template jamps<T, true, false>(q, h, c, J);
+  }
   double v = (double)P::template colour_sum<T>(J);
   if (mehel) mehel[(int64_t)h * nevt + i] = v;
 #pragma unroll
@@ -202,7 +224,12 @@ __global__ void __launch_bounds__(BS)
   double q[P::NPAR][4];
   load_event<P>(mom, i, q);
   cx<T> J[P::NCOL];
-  P::template jamps<T>(q, hl.code[k], c, J);
+  if (__all(beams_on_axis(q))) {
+    set_beams(q);
+    P::template jamps<T, false, true>(q, hl.code[k], c, J);
+  } else {
+    P::template jamps<T, false, false>(q, hl.code[k], c, J);
+  }
   double v = (double)P::template colour_sum<T>(J);
   for (int off = L >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off);
   if (k == 0) {
@@ -265,7 +292,12 @@ __global__ void __launch_bounds__(64)
   double q[P::NPAR][4];
   load_event<P>(mom, i, q);
   cx<float> J[P::NCOL];
-  P::template jamps<float, true>(q, (unsigned)lane, c, J);
+  if (beams_on_axis(q)) {  // wave-uniform
+    set_beams(q);
+    P::template jamps<float, true, true>(q, (unsigned)lane, c, J);
+  } else {
+    P::template jamps<float, true, false>(q, (unsigned)lane, c, J);
+  }
 __shared__ float jl[2 * P::NCOL * 64];
 #pragma unroll
   for (int k = 0; k < P::NCOL; ++k) {
@@ -293,7 +325,7 @@ __shared__ float jl[2 * P::NCOL * 64];
 // evtw; the scan finds none in most waves.
 template <int NPAR>
 __device__ __forceinline__ bool ill_conditioned(const double (&p)[NPAR][4], double kmax) {
-  double m = INFINITY;
+  double m = __DBL_MAX__;
 #pragma unroll
   for (int i = 0; i < NPAR; ++i)
 #pragma unroll

@@ -442,7 +442,7 @@ def emit_body(pd, coefs, order, bils, need, budget, fence_every=4):
         nd = need(k)
         pin = {n.idx for n in nd}
         if pos % fence_every == 0:
-            L.append("  fence<UNI>(p);")
+            L.append("  fence<UNI, BEAM>(p);")
         names = [ensure(n, pos, pin) for n in nd]
         cl, cr = FFV[(d.fin.flav, d.vec.flav)]
         if len(nd) == 2:   # shared bilinear . vector
@@ -635,7 +635,7 @@ def emit_adjoint_body(pd, coefs, order, bils, need, budget, lds=False, lds_span=
     for si, st in enumerate(steps):
         cur_step[0] = si
         if si % ADJ_FENCE_EVERY == 0:
-            L.append("  fence(p);")
+            L.append("  fence<UNI, BEAM>(p);")
         if st[0] == 'amp':
             pos, nd = st[1], st[2]
             k = order[pos]
@@ -865,7 +865,9 @@ def generate(name, orders=None):
         stats[prec] = dict(flops_amp_per_hel=algo, flops_executed_per_hel=execd,
                            peak_live_wavefunctions=peak, recomputed=rec)
         jparam = f"cx<{T}> (&J)[{ncol}]"
-        w("template <bool UNI = false>")
+        w("// UNI: momenta the same in every lane (scalar registers); BEAM: the two")
+        w("// incoming momenta (E,0,0,E) and (E,0,0,-E) with constant zero components")
+        w("template <bool UNI = false, bool BEAM = false>")
         w(f"__device__ __forceinline__ void jamps_{prec}({Rt} (&p)[{npar}][4], unsigned hcode,")
         w(f"                                          const Couplings<{Ct}>& c, {jparam}) {{")
         w(f"  using T = {T};")
@@ -875,11 +877,11 @@ def generate(name, orders=None):
         L.extend(body)
         w("}")
         w("")
-    w("template <typename T, bool UNI = false>")
+    w("template <typename T, bool UNI = false, bool BEAM = false>")
     w(f"__device__ __forceinline__ void jamps(double (&p)[{npar}][4], unsigned hcode,")
     w(f"                                      const Couplings<T>& c, cx<T> (&J)[{ncol}]) {{")
-    w("  if constexpr (sizeof(T) == 8) jamps_f64<UNI>(p, hcode, c, J);")
-    w("  else jamps_f32<UNI>(p, hcode, c, J);")
+    w("  if constexpr (sizeof(T) == 8) jamps_f64<UNI, BEAM>(p, hcode, c, J);")
+    w("  else jamps_f32<UNI, BEAM>(p, hcode, c, J);")
     w("}")
     w("")
     # colour sum: sum_i J_i^* (sum_j C_ij J_j) using the symmetry of C
@@ -917,8 +919,9 @@ def generate(name, orders=None):
             A.append(f"constexpr int ADJ_SLOTS_{prec} = {nslots};")
             A.append(f"// reverse mode: returns the colour-summed |M|^2 of helicity hcode and adds")
             A.append(f"// its gradient with respect to the momenta of the final-state legs to pb;")
-            A.append(f"// ws: the lane's adjoint slots (ws.slot(s), ws.clear(s)) when ADJ_SLOTS > 0")
-            A.append(f"template <class WS>")
+            A.append(f"// ws: the lane's adjoint slots (ws.slot(s), ws.clear(s)) when ADJ_SLOTS > 0;")
+            A.append(f"// BEAM: the incoming momenta on the axis with constant zero components")
+            A.append(f"template <bool BEAM, class WS>")
             A.append(f"__device__ __forceinline__ double adjoint_{prec}(double (&p)[{npar}][4], unsigned hcode,")
             A.append(f"                                            const Couplings<{Ct}>& c,")
             A.append(f"                                            double (&pb)[{npar}][4], const WS& ws) {{")
@@ -982,7 +985,7 @@ def emit_units(name):
   static constexpr int NCOL = gen_{name}::NCOL;
   static constexpr int CDEN = gen_{name}::CDEN;
   __device__ static __forceinline__ const int* cnum() {{ return &gen_{name}::CNUM[0][0]; }}
-  template <typename T, bool UNI = false>
+  template <typename T, bool UNI = false, bool BEAM = false>
   __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<T>& c, cx<T> (&J)[NCOL]) {{
     gen_{name}::{{body}}(p, h, c, J);
@@ -1008,7 +1011,7 @@ def emit_units(name):
         else:
             body = f'  return {epl};\n'
         src = head.format(what=f'{T} amplitudes') + '#include "sigmakin_impl.h"\n\nnamespace mg {\n' \
-            f'#include "{name}.inc"\n\n' + traits.replace('{body}', 'jamps<T, UNI>') + '\n' \
+            f'#include "{name}.inc"\n\n' + traits.replace('{body}', 'jamps<T, UNI, BEAM>') + '\n' \
             f'int launch_sigmakin_{name}_{prec}{sk_args} {{\n{body}}}\n'
         if prec == 'f64':
             src += (f'\n// FP64 recomputation of the ill-conditioned events of a reduced-precision\n'
@@ -1019,20 +1022,17 @@ def emit_units(name):
         units[f'sigmakin_{name}_{prec}.hip'] = src + '\n}  // namespace mg\n'
     # mixed: event-per-lane body for the matrix-core colour sum (jamps_f32m)
     # and, for the helicity-per-lane processes, the FP32 body of that kernel
-    mt = traits.replace('{body}', 'jamps_f32m').replace('template <typename T, bool UNI = false>\n'
-                                                        '  __device__ static __forceinline__ void jamps(',
-                                                        'template <typename T, bool UNI = false>\n'
-                                                        '  __device__ static __forceinline__ void jamps(')
+    mt = traits.replace('{body}', 'jamps_f32m<UNI, BEAM>')
     mt = mt.replace('const Couplings<T>& c, cx<T> (&J)[NCOL]', 'const Couplings<float>& c, cx<float> (&J)[NCOL]')
     src = head.format(what='FP32 amplitudes and the matrix-core colour sum') + \
         '#include "sigmakin_impl.h"\n\nnamespace mg {\n' + f'#include "{name}.inc"\n\n' + mt
     if hpl:
         src += f'''
 struct P_{name}_hpl : P_{name} {{
-  template <typename T, bool UNI = false>
+  template <typename T, bool UNI = false, bool BEAM = false>
   __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<float>& c, cx<float> (&J)[NCOL]) {{
-    gen_{name}::jamps<float, UNI>(p, h, c, J);
+    gen_{name}::jamps<float, UNI, BEAM>(p, h, c, J);
   }}
 }};
 '''
@@ -1052,11 +1052,11 @@ struct P_{name}_hpl : P_{name} {{
             src += f'''
 struct {prec.upper()}_{name} {{
   static constexpr int SLOTS = gen_{name}::ADJ_SLOTS_{prec};
-  template <class WS>
+  template <bool BEAM, class WS>
   __device__ static __forceinline__ double adjoint(double (&p)[gen_{name}::NPAR][4], unsigned h,
                                                    const Couplings<{T}>& c,
                                                    double (&pb)[gen_{name}::NPAR][4], const WS& ws) {{
-    return gen_{name}::adjoint_{prec}(p, h, c, pb, ws);
+    return gen_{name}::adjoint_{prec}<BEAM>(p, h, c, pb, ws);
   }}
 }};
 '''
