@@ -94,6 +94,25 @@ def recorded_traffic(proc, nevt):
     return {}
 
 
+def recorded_flops(proc, nhel):
+    """Algorithmic flops per event of proc's SIGMAKIN code from the ```flops
+    block of profiles/*.md: the executed VALU flops of the FP64 kernel of a
+    build whose amplitude code recomputes nothing
+    (`python -m paper_2106_12631_amd.build --no-recompute`), i.e. the work of
+    the amplitude code as compiled, after the products with the beams' and
+    the massless vectors' zero components have folded away.  None when no
+    record matches the current sources."""
+    import glob
+    import re
+    want = kernel_source_hash(proc)
+    for path in sorted(glob.glob(os.path.join(ROOT, 'profiles', '*.md'))):
+        for blk in re.findall(r"```flops\n(.*?)```", open(path).read(), re.S):
+            rec = json.loads(blk).get(proc)
+            if rec and rec.get('source_hash') == want and rec.get('nhel') == nhel:
+                return rec['flops_per_event']
+    return None
+
+
 # ----------------------------------------------------------------------------- CPU baseline
 def _oracle_eval(kind, proc, seed, start, count):
     """The oracle on events [start, start + count): RNG + RAMBO + |M|^2
@@ -412,7 +431,12 @@ def main():
             eng, wall, k_ms, nonfinite, scopes, me = run_gpu(mg, torch, proc, prec, seed, nevt,
                                                              args.steps, args.warmup)
             nhel = eng.layout.nhel_good
-            flops_evt = (meta['flops_amp_per_hel'] + meta['flops_colour_per_hel']) * nhel
+            generic = (meta['flops_amp_per_hel'] + meta['flops_colour_per_hel']) * nhel
+            flops_evt = recorded_flops(proc, nhel)
+            source = "measured: executed flops of the no-recomputation build"
+            if flops_evt is None:
+                flops_evt = generic
+                source = "generic HELAS routine count (no measurement for these sources)"
             k_avg = sum(k_ms) / len(k_ms) / 1e3
             achieved = flops_evt * nevt / k_avg
             peak = PEAK_FP64_VALU if prec == 'fp64' else PEAK_FP32_VALU
@@ -428,7 +452,8 @@ def main():
                 "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                              "peak": peak / 1e12, "unit": "TFLOP/s",
                              "frac": achieved / peak, "traffic": traffic.get(prec),
-                             "flops_per_event": flops_evt},
+                             "flops_per_event": flops_evt, "flops_source": source,
+                             "generic_flops_per_event": generic},
             }
             if calibration:
                 # against what a stream of independent FMAs of the same

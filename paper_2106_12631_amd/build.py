@@ -8,6 +8,9 @@ file; then build the calibration kernels (calib/) as libmg5cal.so.
     python -m paper_2106_12631_amd.build               build both libraries
     python -m paper_2106_12631_amd.build --resources   print the compiler's
         register, scratch, LDS and occupancy report of every kernel
+    python -m paper_2106_12631_amd.build --no-recompute OUT
+        a measurement library at OUT whose amplitude code recomputes nothing
+        (its executed flops are the algorithmic flops)
 """
 import os
 import subprocess
@@ -56,29 +59,30 @@ def source_flags(src):
     return extra
 
 
-def sources():
+def sources(csrc=CSRC):
     """Hand-written units of csrc/ and the per-process units the generator
     writes to csrc/generated/ (file names are unique across the two)."""
-    gen = os.path.join(CSRC, 'generated')
-    units = [f for f in os.listdir(CSRC) if f.endswith('.hip')]
+    gen = os.path.join(csrc, 'generated')
+    units = [f for f in os.listdir(csrc) if f.endswith('.hip')]
     if os.path.isdir(gen):
         units += [os.path.join('generated', f) for f in os.listdir(gen) if f.endswith('.hip')]
     return sorted(units)
 
 
-def build(force=True, verbose=True, extra_flags=(), output=None):
+def build(force=True, verbose=True, extra_flags=(), output=None, csrc=CSRC, objdir=BUILD):
     sys.path.insert(0, os.path.dirname(HERE))
     from paper_2106_12631_amd.gen import emit
-    emit.write_all(os.path.join(CSRC, 'generated'))
-    os.makedirs(BUILD, exist_ok=True)
+    emit.write_all(os.path.join(csrc, 'generated'))
+    os.makedirs(objdir, exist_ok=True)
+    flags = [csrc if f == CSRC else f for f in FLAGS]
     procs = []
     objs = []
     t0 = time.time()
-    for src in sources():
-        obj = os.path.join(BUILD, os.path.basename(src).replace('.hip', '.o'))
+    for src in sources(csrc):
+        obj = os.path.join(objdir, os.path.basename(src).replace('.hip', '.o'))
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, *source_flags(src), *extra_flags, '-c',
-               os.path.join(CSRC, src), '-o', obj]
+        cmd = [HIPCC, *flags, *source_flags(src), *extra_flags, '-c',
+               os.path.join(csrc, src), '-o', obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
     for src, p in procs:
@@ -108,6 +112,40 @@ def build(force=True, verbose=True, extra_flags=(), output=None):
     if verbose:
         print(f"[build] {lib} in {time.time() - t0:.1f}s", file=sys.stderr)
     return lib
+
+
+# Live-wavefunction budget of the measurement build below: above every
+# process's peak (32 for g g -> t t~ g g), so nothing is recomputed.
+NO_RECOMPUTE_BUDGET = 1 << 20
+
+
+def build_without_recomputation(output):
+    """A library whose generated amplitude code computes every wavefunction
+    once and keeps it until its last use, whatever the register spills: the
+    executed flops of its SIGMAKIN kernels (rocprofv3 VALU flop counters) are
+    the algorithmic flops of the amplitude code as compiled, after the
+    folding of the beam and zero components.  Built from a temporary copy of
+    csrc/; the working tree's generated code and library are left as they
+    are.  Only the amplitude bodies change (the gradient kernels keep their
+    budgets)."""
+    import shutil
+    import tempfile
+    tmp = tempfile.mkdtemp(prefix='mg5mi_norecompute_')
+    keys = ('MG_BUDGET_F64', 'MG_BUDGET_F32', 'MG_BUDGET_F32M')
+    saved = {k: os.environ.get(k) for k in keys}
+    try:
+        csrc = os.path.join(tmp, 'csrc')
+        shutil.copytree(CSRC, csrc, ignore=shutil.ignore_patterns('generated'))
+        for k in keys:
+            os.environ[k] = str(NO_RECOMPUTE_BUDGET)
+        return build(output=os.path.abspath(output), csrc=csrc, objdir=os.path.join(tmp, 'obj'))
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+        shutil.rmtree(tmp, ignore_errors=True)
 
 
 def resource_report():
@@ -149,5 +187,7 @@ def resource_report():
 if __name__ == '__main__':
     if '--resources' in sys.argv:
         print(resource_report())
+    elif '--no-recompute' in sys.argv:
+        build_without_recomputation(sys.argv[sys.argv.index('--no-recompute') + 1])
     else:
         build()

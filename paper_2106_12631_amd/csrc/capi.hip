@@ -5,7 +5,7 @@
 
 #include <new>
 
-#include "../../include/mg5mi.h"
+#include "mg5mi.h"
 #include "internal.h"
 
 namespace mg {

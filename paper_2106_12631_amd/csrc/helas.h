@@ -195,6 +195,10 @@ __device__ __forceinline__ cx<T> inv_den(R re, R im) {
 
 // Opaque copy: the compiler must assume the four components changed, so a
 // wavefunction recomputed from it is not merged with an earlier computation.
+// Components that are constants after inlining (the zero time component of
+// a massless external vector, the zeros of a beam's wavefunction) stay
+// visible: merging cannot happen through them, and the recomputation folds
+// the products with them as the first computation did.
 __device__ __forceinline__ void opaque(double& x) { asm volatile("" : "+v"(x)); }
 __device__ __forceinline__ void opaque(float& x) { asm volatile("" : "+v"(x)); }
 template <typename F>
@@ -206,8 +210,8 @@ template <typename T>
 __device__ __forceinline__ void opaque4(cx<T> (&w)[4]) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    opaque(w[k].r);
-    opaque(w[k].i);
+    if (!__builtin_constant_p(w[k].r)) opaque(w[k].r);
+    if (!__builtin_constant_p(w[k].i)) opaque(w[k].i);
   }
 }
 

@@ -17,7 +17,7 @@
 //   unw_write_kernel   per block: wave ballots + LDS offsets -> idx_out
 #include <mutex>
 
-#include "../../include/mg5mi.h"
+#include "mg5mi.h"
 #include "common.h"
 #include "internal.h"
 #include "philox.h"

@@ -745,17 +745,17 @@ def emit_adjoint_body(pd, coefs, order, bils, need, budget, lds=False, lds_span=
 
 # register budget in live wavefunctions (4 complex each) per precision, the
 # measured best for gg -> t t~ g g on gfx950 (FP64 wavefunctions take 16
-# VGPRs, FP32 ones 8; the colour-flow amplitudes stay live besides them).
-# FP64 16, one helicity per lane: fewer recomputations outweigh a few
-# hundred bytes of spills (13: 19.1, 14: 19.4, 15 and 16: 19.5, 18: 19.3 M
-# MEs/s; with the vector-like vertices 15 to 17 give 20.1-20.3).  FP32 13,
-# one helicity per lane, the largest budget that fits 256 registers (two
-# waves per SIMD): 11: 28.6, 12: 29.7, 13: 32.2 M MEs/s, 14 spills into
-# AGPRs (one wave per SIMD).  'f32m' is the FP32 body of the event-per-lane
-# kernel whose colour sum runs on the matrix cores (28: 23.8, 36: 26.1).
-# The gradient kernel (gg -> t t~ g) takes the same time for FP64 budgets
-# 6 to 12.
-BUDGET = {'f64': 16, 'f32': 13, 'f32m': 36, 'a64': 8, 'a32': 12}
+# VGPRs, FP32 ones 8, fewer where components are zero at compile time; the
+# colour-flow amplitudes stay live besides them).  With the beam bodies
+# (2^19 events, ms): FP64 one helicity per lane 14: 19.5, 16: 19.4, 18:
+# 19.1-19.2, 20: 19.6 (404 B of spills per lane); FP32 one helicity per lane
+# 13: 13.4, 15: 13.2-13.3, the largest budget that fits 256 registers (two
+# waves per SIMD; 17 needs AGPRs, one wave per SIMD: 16.4).  'f32m' is the
+# FP32 body of the event-per-lane kernel whose colour sum runs on the matrix
+# cores (28: 23.8, 36: 26.1 M MEs/s before the beam bodies).  The gradient
+# kernel (gg -> t t~ g, 2^18 events): FP64 budget 8: 4.19 ms, 12 or 14:
+# 4.0-4.1 ms.
+BUDGET = {'f64': 18, 'f32': 15, 'f32m': 36, 'a64': 12, 'a32': 12}
 # processes with a generated reverse-mode (adjoint) body for the gradient kernel
 GRAD_PROCESSES = ('eemumu', 'ggtt', 'ggttg')
 # local-search moves over the diagram order (gg -> t t~ g g at FP64 budget 16:
