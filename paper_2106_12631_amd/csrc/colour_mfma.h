@@ -34,6 +34,10 @@
 //                   chunk c = s G + g holds split s of colours 8g .. 8g+7,
 //                   and C is repeated for the three splits, so one product
 //                   gives C (hi + mid + lo) = C J.
+// The A operands (the colour matrix, the same for every event) are not
+// built on the device: the generator writes them per K block and lane in
+// the layout above (CS_A_F32, CS_A_BF16 of the generated code), and init()
+// loads this lane's.
 // Every lane of the wave must call sum() together (cross-lane operations);
 // the kernels using it run one wave per block.
 #pragma once
@@ -47,9 +51,10 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned uintx4 __attribute__((ext_vector_type(4)));
 
-// exact FP32 -> BF16 bits for values with at most 8 significant bits
-__device__ __forceinline__ unsigned short bf16_exact_bits(float x) {
-  return (unsigned short)(__float_as_uint(x) >> 16);
+// the upper halves of two words in one: (a >> 16 << 16) | (b >> 16), one
+// v_perm_b32 (byte select 2, 3 of b, then 2, 3 of a)
+__device__ __forceinline__ unsigned pack_upper(unsigned a, unsigned b) {
+  return __builtin_amdgcn_perm(a, b, 0x07060302u);
 }
 
 // (lo tile, hi tile) operands from this lane's a and b (see above)
@@ -109,25 +114,15 @@ struct ColourMfmaF32 {
     for (int kb = 0; kb < KB; ++kb) a[kb] = tab[kb * 64 + lane];
   }
 
-  // cnum: the NCOL x NCOL integer numerators of C, row-major.  Every lane
-  // loads an in-range entry and multiplies it by 0 where the tile is padding
-  // (a selected value would let the compiler move each load into a branch
-  // of its own), and all loads are issued before the first is used: one
-  // memory latency instead of one per load.
-  __device__ __forceinline__ void init(const int* cnum, int lane) {
-    const int m = lane & 31, kh = lane >> 5;
-    int v[KB];
+  // the generated table: tab[kb][lane] = C[lane % 32][2 kb + lane / 32]
+  // (numerators, 0 past the matrix)
+  template <class P>
+  __device__ static __forceinline__ const Word* table() {
+    return P::cs_a_f32();
+  }
+  __device__ __forceinline__ void init(const Word* tab, int lane) {
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      const int k = 2 * kb + kh;
-      v[kb] = cnum[(m < NCOL ? m : NCOL - 1) * NCOL + (k < NCOL ? k : NCOL - 1)];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      const int k = 2 * kb + kh;
-      a[kb] = (float)v[kb] * ((m < NCOL && k < NCOL) ? 1.f : 0.f);
-    }
+    for (int kb = 0; kb < KB; ++kb) a[kb] = tab[kb * 64 + lane];
   }
 
   // returns sum_ij C_ij Re(conj(J_i) J_j) (numerators of C) for this lane's event
@@ -179,50 +174,16 @@ struct ColourMfmaBf16 {
     for (int kb = 0; kb < KB; ++kb) a[kb] = __builtin_bit_cast(bf16x8, tab[kb * 64 + lane]);
   }
 
-  // as ColourMfmaF32::init
-  __device__ __forceinline__ void init(const int* cnum, int lane) {
-    const int m = lane & 31, kh = lane >> 5;
-    int v[KB][8];
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      const int g = (2 * kb + kh) % G;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int col = 8 * g + j;
-        v[kb][j] = cnum[(m < NCOL ? m : NCOL - 1) * NCOL + (col < NCOL ? col : NCOL - 1)];
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      const int c = 2 * kb + kh, g = c % G;
-      unsigned u[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        unsigned short h[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const int col = 8 * g + 2 * q + t;
-          h[t] = bf16_exact_bits((float)v[kb][2 * q + t] *
-                                 ((m < NCOL && c < NCH && col < NCOL) ? 1.f : 0.f));
-        }
-        u[q] = (unsigned)h[0] | ((unsigned)h[1] << 16);
-      }
-      const uintx4 v = {u[0], u[1], u[2], u[3]};
-      a[kb] = __builtin_bit_cast(bf16x8, v);
-    }
+  // the generated table: tab[kb][lane] = C[lane % 32][8 g + j], j = 0..7,
+  // g = (2 kb + lane / 32) % G, as eight BF16 numerators (exact: at most 8
+  // significant bits), 0 past the matrix and the last chunk
+  template <class P>
+  __device__ static __forceinline__ const Word* table() {
+    return (const Word*)P::cs_a_bf16();
   }
-
-  // term s (0: hi, 1: mid, 2: lo) of the exact three-term split of v by
-  // truncation, its bits in the upper half of a 32-bit word; computed where
-  // a K block needs it rather than kept for all colours
-  __device__ static __forceinline__ unsigned split(float v, int s) {
-    const unsigned hi = __float_as_uint(v) & 0xFFFF0000u;
-    if (s == 0) return hi;
-    const float r1 = v - __uint_as_float(hi);
-    const unsigned mid = __float_as_uint(r1) & 0xFFFF0000u;
-    if (s == 1) return mid;
-    return __float_as_uint(r1 - __uint_as_float(mid));
+  __device__ __forceinline__ void init(const Word* tab, int lane) {
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) a[kb] = __builtin_bit_cast(bf16x8, tab[kb * 64 + lane]);
   }
 
   __device__ __forceinline__ float sum(const cx<float> (&J)[NCOL], int lane) {
@@ -238,6 +199,19 @@ struct ColourMfmaBf16 {
       float x[NCOL];
 #pragma unroll
       for (int k = 0; k < NCOL; ++k) x[k] = get(part, k);
+      // the exact three-term split of every amplitude by truncation, each
+      // term in the upper half of a word: hi = x, mid = x - hi, lo =
+      // mid's residual (at most 8 significant bits remain: exact in BF16)
+      unsigned t[3][NCOL];
+#pragma unroll
+      for (int k = 0; k < NCOL; ++k) {
+        const unsigned u = __float_as_uint(x[k]);
+        const float r1 = x[k] - __uint_as_float(u & 0xFFFF0000u);
+        const unsigned u1 = __float_as_uint(r1);
+        t[0][k] = u;
+        t[1][k] = u1;
+        t[2][k] = __float_as_uint(r1 - __uint_as_float(u1 & 0xFFFF0000u));
+      }
       floatx16 dlo = {0}, dhi = {0};
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
@@ -246,11 +220,12 @@ struct ColourMfmaBf16 {
         for (int q = 0; q < 4; ++q) {
           unsigned w[2];
 #pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            const int c = 2 * kb + t, s = c / G, g = c % G;
+          for (int h = 0; h < 2; ++h) {
+            // chunk c: term s of colours 8 g + 2 q (low half) and + 1 (high)
+            const int c = 2 * kb + h, s = c / G, g = c % G;
             const int k0 = 8 * g + 2 * q, k1 = k0 + 1;
-            w[t] = c < NCH ? (split(k0 < NCOL ? x[k0] : 0.f, s) >> 16) |
-                                 (split(k1 < NCOL ? x[k1] : 0.f, s) & 0xFFFF0000u)
+            w[h] = c < NCH ? pack_upper(k1 < NCOL ? t[s < 3 ? s : 0][k1] : 0u,
+                                        k0 < NCOL ? t[s < 3 ? s : 0][k0] : 0u)
                            : 0u;
           }
           swap_halves(w[0], w[1], ulo[q], uhi[q]);

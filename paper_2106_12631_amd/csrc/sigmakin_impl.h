@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(64)
   using CSN = CS<P::NCOL>;
   __shared__ typename CSN::Word tab[CSN::KB * 64];
   CSN cs;
-  cs.init(P::cnum(), lane);
+  cs.init(CSN::template table<P>(), lane);
   cs.save(tab, lane);
   const double scale = inv_iden / P::CDEN;
   double q0[P::NPAR][4];
@@ -270,10 +270,11 @@ int sigmakin_group_launch(const MeArgs& a, const Couplings<T>& c, const double* 
 typedef __attribute__((address_space(3))) float lds_float;
 
 template <template <int> class CS, int NCOL>
-__device__ __forceinline__ float colour_sum_mfma_lds(const lds_float* jl, const int* cnum,
+__device__ __forceinline__ float colour_sum_mfma_lds(const lds_float* jl,
+                                                     const typename CS<NCOL>::Word* tab,
                                                      int lane) {
   CS<NCOL> cs;
-  cs.init(cnum, lane);
+  cs.init(tab, lane);
   return cs.sum_parts([&](int part, int k) { return jl[(2 * k + part) * 64 + lane]; },
                       [&](int kb) { return cs.a[kb]; }, lane);
 }
@@ -304,7 +305,8 @@ __shared__ float jl[2 * P::NCOL * 64];
     jl[(2 * k) * 64 + lane] = J[k].r;
     jl[(2 * k + 1) * 64 + lane] = J[k].i;
   }
-  double v = (double)colour_sum_mfma_lds<CS, P::NCOL>((const lds_float*)jl, P::cnum(), lane);
+  double v = (double)colour_sum_mfma_lds<CS, P::NCOL>(
+      (const lds_float*)jl, CS<P::NCOL>::template table<P>(), lane);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   if (lane == 0) {

@@ -47,6 +47,50 @@ class Bil:
         self.op = ('bil', fout, fin)
 
 
+def _f32_bits(v):
+    import struct
+    return struct.unpack('<I', struct.pack('<f', float(v)))[0]
+
+
+def colour_mfma_tables(cnum, ncol):
+    """The A operands of the matrix-core colour sum (csrc/colour_mfma.h) for
+    the numerators cnum, per K block kb and lane l (m = l % 32 the row of C,
+    kh = l / 32 the half of the K block):
+      F32:  one float, C[m][2 kb + kh];
+      BF16: eight BF16 values packed two per 32-bit word, low half first:
+            C[m][8 g + j], j = 0..7, g = (2 kb + kh) % G for the chunk
+            c = 2 kb + kh of the three-way split (the split index does not
+            change C), zero past the matrix and the last chunk.
+    Every numerator has at most 8 significant bits, so its BF16 bits are the
+    upper half of its FP32 bits."""
+    kbf = (ncol + 1) // 2
+    f32 = [[float(cnum[l & 31][2 * kb + (l >> 5)])
+            if (l & 31) < ncol and 2 * kb + (l >> 5) < ncol else 0.0
+            for l in range(64)] for kb in range(kbf)]
+    g_ = (ncol + 7) // 8
+    nch = 3 * g_
+    kbb = (nch + 1) // 2
+    bf16 = []
+    for kb in range(kbb):
+        row = []
+        for l in range(64):
+            m, c = l & 31, 2 * kb + (l >> 5)
+            g = c % g_
+            words = []
+            for q in range(4):
+                half = []
+                for t in range(2):
+                    col = 8 * g + 2 * q + t
+                    v = cnum[m][col] if (m < ncol and c < nch and col < ncol) else 0
+                    bits = _f32_bits(v)
+                    assert bits & 0xFFFF == 0, "numerator not exact in BF16"
+                    half.append(bits >> 16)
+                words.append(half[0] | (half[1] << 16))
+            row.append(words)
+        bf16.append(row)
+    return f32, bf16
+
+
 def _deps(n):
     return [c for c in n.op[1:] if hasattr(c, 'idx')]
 
@@ -851,6 +895,16 @@ def generate(name, orders=None):
     for row in cnum:
         w("  {" + ", ".join(str(x) for x in row) + "},")
     w("};")
+    f32t, bf16t = colour_mfma_tables(cnum, ncol)
+    w("// A operands of the matrix-core colour sum (colour_mfma.h), per K block and lane")
+    w(f"__device__ const float CS_A_F32[{len(f32t)}][64] = {{")
+    for row in f32t:
+        w("  {" + ", ".join(f"{v:.1f}f" for v in row) + "},")
+    w("};")
+    w(f"__device__ const unsigned CS_A_BF16[{len(bf16t)}][64][4] __attribute__((aligned(16))) = {{")
+    for row in bf16t:
+        w("  {" + ", ".join("{" + ", ".join(f"0x{x:08x}u" for x in words) + "}" for words in row) + "},")
+    w("};")
     w("")
     stats = {}
     variants = [('f64', 'double', 'double', 'double'), ('f32', 'float', 'double', 'float'),
@@ -984,7 +1038,8 @@ def emit_units(name):
   static constexpr int NPAR = gen_{name}::NPAR;
   static constexpr int NCOL = gen_{name}::NCOL;
   static constexpr int CDEN = gen_{name}::CDEN;
-  __device__ static __forceinline__ const int* cnum() {{ return &gen_{name}::CNUM[0][0]; }}
+  __device__ static __forceinline__ const float* cs_a_f32() {{ return &gen_{name}::CS_A_F32[0][0]; }}
+  __device__ static __forceinline__ const unsigned* cs_a_bf16() {{ return &gen_{name}::CS_A_BF16[0][0][0]; }}
   template <typename T, bool UNI = false, bool BEAM = false>
   __device__ static __forceinline__ void jamps(double (&p)[NPAR][4], unsigned h,
                                                const Couplings<T>& c, cx<T> (&J)[NCOL]) {{
