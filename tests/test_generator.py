@@ -10,6 +10,9 @@
 * The recorded schedules of the generated code (written by the build)
   respect the same bounds, and its process constants match the diagram and
   colour counts.
+* The matrix-core operand tables of the colour matrix decode, in the lane
+  layout of the 32x32 MFMA tiles, back to the colour matrix: every row and
+  column of C once per split chunk, zeros in the padding.
 * bench.py refuses more than one GPU with a message and exit status 2.
 """
 import json
@@ -73,6 +76,46 @@ def test_generated_code_metadata():
     s = meta['ggttgg']['schedule']
     assert s['f64']['flops_executed_per_hel'] < s['f32']['flops_executed_per_hel']
     assert s['f32m']['recomputed'] == 0
+
+
+@pytest.mark.parametrize('proc', ['ggtt', 'ggttg', 'ggttgg'])
+def test_colour_mfma_tables_decode_to_the_colour_matrix(proc):
+    import struct
+    from paper_2106_12631_amd.gen import emit
+    from paper_2106_12631_amd.gen.diagrams import ProcessDiagrams, colour_matrix
+    pd = ProcessDiagrams(proc)
+    basis = pd.colour_basis()
+    n = len(basis)
+    cnum, _ = colour_matrix(basis, len(pd.gluons))
+    f32, bf16 = emit.colour_mfma_tables(cnum, n)
+
+    def bf16_value(h):
+        return struct.unpack('<f', struct.pack('<I', h << 16))[0]
+
+    # F32: lane l of K block kb holds A[m = l % 32][k = 2 kb + l / 32]
+    A = {}
+    for kb, row in enumerate(f32):
+        for lane, v in enumerate(row):
+            A[(lane % 32, 2 * kb + lane // 32)] = v
+    for (m, k), v in A.items():
+        assert v == (cnum[m][k] if m < n and k < n else 0.0)
+    assert all((m, k) in A for m in range(n) for k in range(n))
+    # BF16: lane l of K block kb holds the eight K entries of chunk
+    # c = 2 kb + l / 32, chunk c = s G + g covering colours 8 g .. 8 g + 7
+    G = (n + 7) // 8
+    seen = {}
+    for kb, row in enumerate(bf16):
+        for lane, words in enumerate(row):
+            m, c = lane % 32, 2 * kb + lane // 32
+            vals = [bf16_value((w >> (16 * t)) & 0xFFFF) for w in words for t in (0, 1)]
+            for j, v in enumerate(vals):
+                col = 8 * (c % G) + j
+                if m < n and c < 3 * G and col < n:
+                    assert v == cnum[m][col]
+                    seen[(c // G, m, col)] = True
+                else:
+                    assert v == 0.0
+    assert len(seen) == 3 * n * n
 
 
 def test_bench_refuses_several_gpus():
