@@ -263,7 +263,7 @@ int sigmakin_group_launch(const MeArgs& a, const Couplings<T>& c, const double* 
 // through LDS, jl[(2 k + part) * 64 + lane] (each lane reads back only its
 // own values, so no barrier is needed): with the MFMA results in VGPRs
 // (-amdgpu-mfma-vgpr-form, a flag of the mixed sources) the kernel keeps the
-// register allocation of the FP32 amplitude body, 249 VGPRs, no AGPRs and
+// register allocation of the FP32 amplitude body, 253 VGPRs, no AGPRs and
 // no scratch: two waves per SIMD.  (Out of line behind a call it needed a
 // 72-byte stack frame per lane and ran 1.8 % slower; with the amplitudes
 // passed in registers instead of LDS, 0.4 % slower.)
