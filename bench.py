@@ -261,13 +261,54 @@ def run_gpu(mg, torch, proc, prec, seed, nevt, steps, warmup):
         evd[k][1].record(stream)
     torch.cuda.synchronize()
     d2h_ms = [a.elapsed_time(b) for a, b in evd]
+    graph = graph_step(eng, torch, seed, nevt, mom, wgt, me, steps)
     scopes = {
         "sigmakin": nevt / (_median(k_ms) / 1e3),
         "sample_sigmakin": nevt / (_median(step_ms) / 1e3),
         "sample_sigmakin_dtoh": nevt / (_median(d2h_ms) / 1e3),
+        "sample_sigmakin_graph": nevt / (_median(graph["step_ms"]) / 1e3),
         "unit": "MEs/s (median over the timed steps)",
     }
-    return eng, wall, k_ms, nonfinite, scopes, me
+    return eng, wall, k_ms, nonfinite, scopes, me, graph
+
+
+def graph_step(eng, torch, seed, nevt, mom, wgt, me, steps):
+    """The step (sampler + SIGMAKIN) captured once in a HIP graph and
+    replayed: one graph launch per step instead of two library calls, for
+    the launch-bound workloads.  The library's calls only enqueue kernels on
+    the caller's stream (no allocation, no synchronisation), so they capture
+    as they are.  Every checked replay must reproduce the eager step's
+    matrix elements bit for bit (eager work and synchronisations between
+    them).  Returns the per-step HIP-event times and the wall-clock rate of
+    back-to-back replays."""
+    ref = me.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        eng.sample(seed, nevt, mom=mom, wgt=wgt)
+        eng.sigmakin(mom, nevt, me=me)
+    stream = torch.cuda.current_stream()
+    same = True
+    for _ in range(3):
+        me.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(me, ref))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for a, b in evs:
+        a.record(stream)
+        g.replay()
+        b.record(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    same = same and bool(torch.equal(me, ref))
+    return {"step_ms": [a.elapsed_time(b) for a, b in evs], "wall_MEs_per_s": nevt * steps / wall,
+            "replays_equal_eager": same}
 
 
 def mfma_work(ncol, nhel, prec, proc, seconds, nevt):
@@ -428,8 +469,8 @@ def main():
         traffic = recorded_traffic(proc, nevt)
         for prec in precs:
             print(f"[bench] {name} {prec} {nevt} events", file=sys.stderr, flush=True)
-            eng, wall, k_ms, nonfinite, scopes, me = run_gpu(mg, torch, proc, prec, seed, nevt,
-                                                             args.steps, args.warmup)
+            eng, wall, k_ms, nonfinite, scopes, me, graph = run_gpu(mg, torch, proc, prec, seed,
+                                                                    nevt, args.steps, args.warmup)
             nhel = eng.layout.nhel_good
             generic = (meta['flops_amp_per_hel'] + meta['flops_colour_per_hel']) * nhel
             flops_evt = recorded_flops(proc, nhel)
@@ -449,6 +490,9 @@ def main():
                 "sigmakin_ms": k_avg * 1e3,
                 "nonfinite": nonfinite,
                 "scopes": scopes,
+                "graph": {"value": graph["wall_MEs_per_s"],
+                          "unit": "MEs/s (sampler + SIGMAKIN replayed from one HIP graph, wall clock)",
+                          "replays_equal_eager": graph["replays_equal_eager"]},
                 "roofline": {"bound": "alu", "achieved": achieved / 1e12,
                              "peak": peak / 1e12, "unit": "TFLOP/s",
                              "frac": achieved / peak, "traffic": traffic.get(prec),
@@ -483,10 +527,12 @@ def main():
     if do_plateau:
         proc, nevt, seed, prec = PLATEAU
         print(f"[bench] plateau {proc} {nevt} events", file=sys.stderr, flush=True)
-        eng, wall, k_ms, nonfinite, scopes, me = run_gpu(mg, torch, proc, prec, seed, nevt,
-                                                         args.steps, args.warmup)
+        eng, wall, k_ms, nonfinite, scopes, me, graph = run_gpu(mg, torch, proc, prec, seed, nevt,
+                                                                args.steps, args.warmup)
         plateau = {"workload": f"{proc} {nevt} events seed {seed}", "precision": prec,
                    "value": nevt * args.steps / wall, "scopes": scopes,
+                   "graph": {"value": graph["wall_MEs_per_s"],
+                             "replays_equal_eager": graph["replays_equal_eager"]},
                    "sigmakin_ms": sum(k_ms) / len(k_ms), "nonfinite": nonfinite}
         del eng, me
         torch.cuda.empty_cache()
