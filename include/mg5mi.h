@@ -19,6 +19,9 @@
  *     are host arithmetic only.
  *   - A handle is immutable after mg_create; any number of streams may use
  *     it concurrently with disjoint outputs.
+ *   - Apart from mg_create, the calls that take a stream only enqueue
+ *     kernels (no allocation, no synchronisation, no memset), so a
+ *     sequence of them can be captured into a HIP graph on that stream.
  *
  * Layouts (AoSoA, Sec. IV.b "AOSOA"; page sizes from mg_layout):
  *   rnd  [ceil(nevt/neppR)][nrnd][neppR]    uniforms, irnd = 4*ifinal + k
@@ -158,7 +161,12 @@ int mg_sample(const mg_handle_t* h, uint64_t seed, int64_t evt_offset, int64_t n
 
 /* Matrix elements (Sec. II, SIGMAKIN): me[i] = (1/IDEN) sum over kept
  * helicities and all colours of |M|^2 for the momenta of event i.
- * If both wgt_or_null and evtw_or_null are given, evtw[i] = wgt[i]*me[i]. */
+ * If both wgt_or_null and evtw_or_null are given, evtw[i] = wgt[i]*me[i].
+ * Any momenta are accepted.  Events whose incoming momenta are exactly
+ * (E,0,0,E) and (E,0,0,-E), as mg_rambo writes them, take a faster body of
+ * the same arithmetic with those zero components as constants (checked per
+ * event where an event has a wave of its own, else for all the events of a
+ * wave together); the two bodies agree to rounding. */
 int mg_sigmakin(const mg_handle_t* h, const double* mom, int64_t nevt, double* me,
                 const double* wgt_or_null, double* evtw_or_null, void* stream);
 
