@@ -57,6 +57,30 @@ __device__ __forceinline__ void load_event(const double* __restrict__ mom, int64
     for (int m = 0; m < 4; ++m) p[ip][m] = mom[aosoa_mom(i, ip, m, P::NPAR)];
 }
 
+// The momenta of event i for one pass of a helicity loop.  With REREAD they
+// are read again (cache hits) through an event index the compiler cannot see
+// through, so that no helicity-independent subexpression (momentum sums,
+// propagator denominators) is hoisted out of the loop and kept live across
+// it: for the processes whose amplitude code fills the register file,
+// recomputing them is cheap and keeping them is not.  Otherwise the copy q0
+// loaded before the loop is used and those parts are computed once per
+// event.  (The generator sets REREAD_MOMENTA per process and kernel.)
+template <class P, bool REREAD>
+__device__ __forceinline__ void event_momenta(const double* __restrict__ mom, int64_t i,
+                                              const double (&q0)[P::NPAR][4],
+                                              double (&q)[P::NPAR][4]) {
+  if constexpr (REREAD) {
+    int64_t iq = i;
+    asm volatile("" : "+v"(iq));
+    load_event<P>(mom, iq, q);
+  } else {
+#pragma unroll
+    for (int ip = 0; ip < P::NPAR; ++ip)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) q[ip][m] = q0[ip][m];
+  }
+}
+
 // me[i] = inv_iden * sum_k |M|^2(helicity hl.code[k]); with mehel != null the
 // per-helicity values are also stored at mehel[hl.code[k] * nevt + i].
 template <class P, typename T, int BS>
@@ -73,15 +97,8 @@ __global__ void __launch_bounds__(BS)
     double acc = 0.0;
 #pragma nounroll
     for (int k = 0; k < hl.n; ++k) {
-      // The momenta are re-read (cache hits) through an event index the
-      // compiler cannot see through, so that no helicity-independent
-      // subexpression (momentum sums, propagator denominators) is hoisted
-      // out of the loop and kept live across it: recomputing them is cheap,
-      // keeping them in registers is not.
-      int64_t iq = i;
-      asm volatile("" : "+v"(iq));
       double q[P::NPAR][4];
-      load_event<P>(mom, iq, q);
+      event_momenta<P, P::REREAD_MOMENTA>(mom, i, q0, q);
       if constexpr (B) set_beams(q);
       cx<T> J[P::NCOL];
       P::template jamps<T, false, B>(q, hl.code[k], c, J);
@@ -126,10 +143,8 @@ __global__ void __launch_bounds__(64)
     double acc = 0.0;
 #pragma nounroll
     for (int k = 0; k < hl.n; ++k) {
-      int64_t iq = il;
-      asm volatile("" : "+v"(iq));
       double q[P::NPAR][4];
-      load_event<P>(mom, iq, q);
+      event_momenta<P, P::REREAD_MOMENTA>(mom, il, q0, q);
       if constexpr (B) set_beams(q);
       cx<float> J[P::NCOL];
       P::template jamps<float, false, B>(q, hl.code[k], c, J);

@@ -1024,6 +1024,18 @@ HPL_PROCESSES = ('ggttgg',)
 # 2^20, equal at 2^24; g g -> t t~ 5.6x at 4096, 1.01x at 2^17, 0.97x from
 # 2^18; g g -> t t~ g 9.6x at 4096, 1.5x at 2^15, 0.87x from 2^16)
 GROUP_MAX_EVENTS = {'eemumu': 1 << 21, 'ggtt': 1 << 17, 'ggttg': 1 << 16}
+# Processes whose event-per-lane kernels re-read the momenta for every
+# helicity (REREAD_MOMENTA, sigmakin_impl.h): those whose amplitude code
+# fills the register file.  The others load them once per event and compute
+# the helicity-independent parts once (2^20 events, FP64 / FP32 amplitudes /
+# mixed, against re-reading: e+e- -> mu+mu- (2^24) +18 % / - / +14 %,
+# g g -> t t~ +3.5 % / +11 % / +9 %, g g -> t t~ g +4.4 % / - / -13 %: the
+# mixed kernel then needs 274 registers, one wave per SIMD).
+REREAD_MOMENTA = {'sigmakin': ('ggttgg',), 'mixed': ('ggttg', 'ggttgg')}
+
+
+def _cbool(b):
+    return 'true' if b else 'false'
 
 
 def emit_units(name):
@@ -1035,6 +1047,7 @@ def emit_units(name):
     head = (f'// Generated for {name}: do not edit.  Kernels of sigmakin_impl.h for this\n'
             f'// process, {{what}}.\n')
     traits = f'''struct P_{name} {{
+  static constexpr bool REREAD_MOMENTA = {{reread}};
   static constexpr int NPAR = gen_{name}::NPAR;
   static constexpr int NCOL = gen_{name}::NCOL;
   static constexpr int CDEN = gen_{name}::CDEN;
@@ -1066,7 +1079,8 @@ def emit_units(name):
         else:
             body = f'  return {epl};\n'
         src = head.format(what=f'{T} amplitudes') + '#include "sigmakin_impl.h"\n\nnamespace mg {\n' \
-            f'#include "{name}.inc"\n\n' + traits.replace('{body}', 'jamps<T, UNI, BEAM>') + '\n' \
+            f'#include "{name}.inc"\n\n' + traits.replace('{body}', 'jamps<T, UNI, BEAM>').replace(
+                '{reread}', _cbool(name in REREAD_MOMENTA['sigmakin'])) + '\n' \
             f'int launch_sigmakin_{name}_{prec}{sk_args} {{\n{body}}}\n'
         if prec == 'f64':
             src += (f'\n// FP64 recomputation of the ill-conditioned events of a reduced-precision\n'
@@ -1077,7 +1091,8 @@ def emit_units(name):
         units[f'sigmakin_{name}_{prec}.hip'] = src + '\n}  // namespace mg\n'
     # mixed: event-per-lane body for the matrix-core colour sum (jamps_f32m)
     # and, for the helicity-per-lane processes, the FP32 body of that kernel
-    mt = traits.replace('{body}', 'jamps_f32m<UNI, BEAM>')
+    mt = traits.replace('{body}', 'jamps_f32m<UNI, BEAM>').replace(
+        '{reread}', _cbool(name in REREAD_MOMENTA['mixed']))
     mt = mt.replace('const Couplings<T>& c, cx<T> (&J)[NCOL]', 'const Couplings<float>& c, cx<float> (&J)[NCOL]')
     src = head.format(what='FP32 amplitudes and the matrix-core colour sum') + \
         '#include "sigmakin_impl.h"\n\nnamespace mg {\n' + f'#include "{name}.inc"\n\n' + mt
