@@ -1020,10 +1020,11 @@ HPL_PROCESSES = ('ggttgg',)
 # Launches of fewer events than this use the group kernel (one kept helicity
 # per lane, several lanes per event) instead of the event-per-lane kernel:
 # the crossovers of the events-per-launch sweep (FP64, SIGMAKIN only; group
-# against event per lane: e+e- -> mu+mu- 1.9x at 4096-16384 events, 1.04x at
-# 2^20, equal at 2^24; g g -> t t~ 5.6x at 4096, 1.01x at 2^17, 0.97x from
-# 2^18; g g -> t t~ g 9.6x at 4096, 1.5x at 2^15, 0.87x from 2^16)
-GROUP_MAX_EVENTS = {'eemumu': 1 << 21, 'ggtt': 1 << 17, 'ggttg': 1 << 16}
+# against event per lane with the momenta loaded once: e+e- -> mu+mu- 1.4x
+# at 4096-16384 events, 1.22x at 2^15, 0.94x at 2^16, 0.77x at 2^20;
+# g g -> t t~ 4.0x at 4096, 1.55x at 2^15, 0.96x at 2^16; g g -> t t~ g 8.0x
+# at 4096, 1.36x at 2^15, 0.77x at 2^16)
+GROUP_MAX_EVENTS = {'eemumu': 1 << 16, 'ggtt': 1 << 16, 'ggttg': 1 << 16}
 # Processes whose event-per-lane kernels re-read the momenta for every
 # helicity (REREAD_MOMENTA, sigmakin_impl.h): those whose amplitude code
 # fills the register file.  The others load them once per event and compute

@@ -284,8 +284,8 @@ def test_module_shortcuts(mg):
     assert torch.equal(r, orc.sample('ggttgg', 3, 0, n)[0])
 
 
-@pytest.mark.parametrize('proc,n', [('ggtt', (1 << 17) + 37), ('ggttg', (1 << 16) + 37),
-                                    ('eemumu', (1 << 21) + 37)])
+@pytest.mark.parametrize('proc,n', [('ggtt', (1 << 16) + 37), ('ggttg', (1 << 16) + 37),
+                                    ('eemumu', (1 << 16) + 37)])
 def test_event_per_lane_above_the_group_threshold(mg, proc, n):
     """Launches above a process's group threshold take the event-per-lane
     kernel (below it, several lanes per event): a ragged launch of that size
