@@ -13,6 +13,9 @@
 * The matrix-core operand tables of the colour matrix decode, in the lane
   layout of the 32x32 MFMA tiles, back to the colour matrix: every row and
   column of C once per split chunk, zeros in the padding.
+* The register budget of the measurement build (build.py --no-recompute,
+  whose executed flops are taken as the algorithmic flops) leaves nothing
+  to recompute in any process's amplitude code.
 * bench.py refuses more than one GPU with a message and exit status 2.
 """
 import json
@@ -116,6 +119,19 @@ def test_colour_mfma_tables_decode_to_the_colour_matrix(proc):
                 else:
                     assert v == 0.0
     assert len(seen) == 3 * n * n
+
+
+@pytest.mark.parametrize('proc', ['eemumu', 'ggtt', 'ggttg', 'ggttgg'])
+def test_measurement_build_budget_recomputes_nothing(proc):
+    from paper_2106_12631_amd import build
+    from paper_2106_12631_amd.gen import emit
+    from paper_2106_12631_amd.gen.diagrams import ProcessDiagrams
+    pd = ProcessDiagrams(proc)
+    order, bils, need = emit.schedule(pd)
+    budget = build.NO_RECOMPUTE_BUDGET
+    _, algo, execd, peak, rec = emit.emit_body(pd, pd.jamp_coefficients(), order, bils, need,
+                                               budget)
+    assert rec == 0 and execd == algo and peak < budget
 
 
 def test_bench_refuses_several_gpus():
